@@ -1,0 +1,133 @@
+"""Pins of the oracle's extrapolator design (table row A0).
+
+The paper leaves the design method open (Sec. II: an optimization between
+filter length and angle; accurate designs are needed for stability).  These
+tests tie the oracle's weighted least-squares design to things fixed outside
+it: the DCT-II (textbook special case), the Bernstein bound for trigonometric
+polynomials (stability), the zero-thickness identity, and an independently
+coded phase-shift target for the reported passband error.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import oracle
+from paper_1912_05529_amd import synth
+
+
+def _phase_shift(kappa, theta, dx, dz):
+    """exp(i kz dz) in physical units: k = kappa/dx, kx = theta/dx."""
+    k = kappa / dx
+    kx = theta / dx
+    kz2 = k * k - kx * kx
+    out = np.where(kz2 >= 0, np.exp(1j * np.sqrt(np.abs(kz2)) * dz),
+                   np.exp(-np.sqrt(np.abs(kz2)) * dz))
+    return out
+
+
+def _entries(desc):
+    dk = (desc.kmax - desc.kmin) / (desc.nk - 1)
+    return (desc.kmin + np.arange(desc.nk) * dk) * desc.dx
+
+
+def _response(tab, theta):
+    """H(theta) = h0 + 2 sum h_n cos(n theta) for every table row."""
+    K = tab.shape[1]
+    C = np.cos(np.outer(np.arange(K), theta))
+    C[1:] *= 2.0
+    return tab @ C
+
+
+@pytest.mark.parametrize("ntaps,L,dz", [(5, 64, 10.0), (25, 256, 10.0), (35, 256, 4.0)])
+def test_p1_dct_special_case(ntaps, L, dz):
+    """w = 1, lambda = 0, no reweighting, no scale: the LS taps are the DCT-II
+    coefficients of the target on the midpoint grid (orthogonality of cos(n
+    theta_i) there), h_n = y_n / (2L)."""
+    desc = synth.TableDesc(ntaps=ntaps, nk=9, kmin=0.01, kmax=0.45, dx=10.0, dz=dz,
+                           w_pass=1.0, w_trans=1.0, w_evan=1.0, ngrid=L, ncheck=64,
+                           nreweight=0, lam=0.0)
+    tab, _, _, sc = oracle.design_table(desc, apply_scale=False)
+    assert np.all(sc == 1.0)
+    theta = (np.arange(L) + 0.5) * math.pi / L
+    K = (ntaps - 1) // 2 + 1
+    for j, kappa in enumerate(_entries(desc)):
+        D = _phase_shift(kappa, theta, desc.dx, desc.dz)
+        y = scipy.fft.dct(D.real, type=2) + 1j * scipy.fft.dct(D.imag, type=2)
+        ref = y[:K] / (2.0 * L)
+        err = np.abs(tab[j] - ref).max() / np.abs(ref).max()
+        assert err < 1e-13, (j, err)
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+def test_p2_stability_every_entry(which, cfg1_table, cfg2_table):
+    """|H_j(kx)| <= 1 for every entry, FP64 and FP32-rounded, on a 65,536-point
+    midpoint grid with the cos(M pi / 2Lf) Bernstein factor (rigorous sup)."""
+    tab = (cfg1_table if which == "cfg1" else cfg2_table)[0]
+    M = tab.shape[1] - 1
+    Lf = 65536
+    theta = (np.arange(Lf) + 0.5) * math.pi / Lf
+    factor = 1.0 / math.cos(M * math.pi / (2 * Lf))
+    for t in (tab, tab.astype(np.complex64).astype(np.complex128)):
+        worst = 0.0
+        for c0 in range(0, t.shape[0], 128):
+            H = _response(t[c0:c0 + 128], theta)
+            worst = max(worst, float(np.abs(H).max()))
+        assert worst * factor <= 1.0, worst * factor
+
+
+def test_p3_design_quality_cfg1(cfg1, cfg1_table):
+    """Passband error against an independently coded phase shift matches the
+    reported value, is below the sanity bound, and the stability scale stays
+    >= 0.9999 (the design is stable by itself, not by attenuation)."""
+    tab, mg, pe, sc = cfg1_table
+    d = cfg1.desc
+    assert sc.min() >= 0.9999
+    assert pe.max() <= 0.05
+    L = d.ngrid
+    theta = (np.arange(L) + 0.5) * math.pi / L
+    H = _response(tab, theta)
+    for j, kappa in enumerate(_entries(d)):
+        pas = theta <= kappa * math.sin(math.radians(d.theta_max_deg))
+        if not pas.any():
+            assert pe[j] == 0.0
+            continue
+        D = _phase_shift(kappa, theta[pas], d.dx, d.dz)
+        e = np.abs(H[j, pas] - D).max()
+        assert abs(e - pe[j]) <= 1e-12, (j, e, pe[j])
+
+
+def test_p3_design_quality_cfg2(cfg2_model, cfg2_table):
+    tab, mg, pe, sc = cfg2_table
+    kap = _entries(cfg2_model.desc)
+    assert sc.min() >= 0.9999
+    assert pe[kap <= 3.25].max() <= 0.03
+    assert pe.max() <= 0.1
+    assert mg.max() <= 1.0
+
+
+def test_p6_zero_thickness_is_identity():
+    """dz = 0 makes the target 1 everywhere, so the taps are a unit impulse and
+    every image row equals row 0."""
+    rng = np.random.default_rng(5)
+    desc = synth.TableDesc(ntaps=15, nk=16, kmin=0.02, kmax=0.4, dx=10.0, dz=0.0,
+                           ngrid=256, ncheck=1024, lam=0.0)
+    tab, _, _, _ = oracle.design_table(desc, apply_scale=False)
+    assert abs(tab[:, 0] - 1.0).max() < 1e-12
+    assert np.abs(tab[:, 1:]).max() < 1e-12
+    nx, nz, nw = 40, 6, 5
+    vel = rng.uniform(700, 2500, (nz, nx)).astype(np.float32)
+    om = synth.omegas(nw, 5, 55)
+    data = rng.standard_normal((nx, nw)) + 1j * rng.standard_normal((nx, nw))
+    img = oracle.migrate(desc, tab, om, vel, data)
+    assert np.abs(img - img[0][None, :]).max() <= 1e-11 * np.abs(img[0]).max()
+
+
+def test_design_rejects_bad_descriptor():
+    bad = synth.TableDesc(ntaps=4, nk=8, kmin=0.01, kmax=0.4, dx=10.0, dz=10.0)
+    with pytest.raises(RuntimeError):
+        oracle.design_table(bad)
+    bad = synth.TableDesc(ntaps=5, nk=8, kmin=0.4, kmax=0.1, dx=10.0, dz=10.0)
+    with pytest.raises(RuntimeError):
+        oracle.design_table(bad)
