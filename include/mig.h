@@ -1,0 +1,214 @@
+/*
+ * mig.h -- C ABI of libmig.so: explicit f-x poststack depth migration on
+ * AMD Instinct MI355X (gfx950), hand-written HIP kernels.
+ *
+ * The method (Shawahna, Salam & Al-Mouhamed, arXiv 1912.05529):
+ *   - the zero-offset section is transformed along t to frequency (Algorithm 1,
+ *     first step; done by the caller);
+ *   - for every depth step z_k -> z_{k+1} = z_k + dz and every frequency
+ *     omega_r, each lateral point x_i of the next plane is the spatial
+ *     convolution of Eq. (1),
+ *         P_{k+1}[x_i][r] = sum_{n=-M..M} h[n] P_k[x_{i-n}][r],  N = 2M+1,
+ *     with a predesigned FIR extrapolator h chosen per point by the wavenumber
+ *     omega_r / v(x_i, z_k) (Algorithm 1 "look-up table"; Sec. III: the cutoff
+ *     varies from point to point);
+ *   - the image row of depth z_k is the sum of the plane over frequencies
+ *     (Algorithm 1 "depth row by summing over frequencies"; Sec. III second
+ *     kernel), taken here as Re sum_r P_k[x][r] (zero-time imaging).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller (e.g. torch
+ *     tensor storage).  Descriptors are host memory, read during the call only.
+ *     The library keeps no state between calls and allocates no memory: scratch
+ *     comes from the caller's workspace `ws` (size from the *_workspace_size
+ *     queries).  Calls are reentrant.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued on it; results are valid once the stream has completed.
+ *     Only mig_design_table synchronizes (it reads back a stability flag).
+ *   - Complex numbers are interleaved (re, im): mig_c64 / mig_c128 have the
+ *     memory layout of torch.complex64 / torch.complex128.
+ *   - Wavefield planes are [nx][nw] (frequency fastest), as produced by a
+ *     transform along t of a [nx][nt] section.  Velocities are float32 [rows][nx]
+ *     PROPAGATION velocities in m/s (for exploding-reflector zero-offset data
+ *     pass half the medium velocity).  Frequencies omega are float64 [nw] in
+ *     rad/s.  Images and rows are float64 [rows][nx].
+ *   - Host-side validation (NULL pointers, non-positive sizes, even N, bad
+ *     table range, aliasing, short workspace) returns a negative code before
+ *     anything is launched.  A failed launch returns MIG_E_DEVICE.  No C++
+ *     exception crosses this interface.
+ *   - Velocities are not checked on the device: a velocity that is not > 0
+ *     (zero, negative, NaN) selects table entry 0.
+ */
+#ifndef MIG_H
+#define MIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MIG_API __attribute__((visibility("default")))
+
+typedef struct { float re, im; } mig_c64;
+typedef struct { double re, im; } mig_c128;
+
+enum {
+    MIG_OK = 0,
+    MIG_E_ARG = -1,        /* invalid argument (host-side check)            */
+    MIG_E_UNSTABLE = -2,   /* designed table failed the |H| <= 1 check      */
+    MIG_E_DEVICE = -3,     /* HIP launch or runtime error                   */
+    MIG_E_WORKSPACE = -4   /* workspace missing or smaller than required    */
+};
+
+/* Largest supported sizes. */
+#define MIG_MAX_NTAPS 63     /* N odd, 1..63 (M = (N-1)/2 <= 31)              */
+#define MIG_MAX_NX 8192      /* lateral points per section                    */
+#define MIG_MAX_NW 1048576   /* frequencies per call                          */
+
+/*
+ * Extrapolator-table descriptor.  Entry j (0 <= j < nk) is designed for the
+ * wavenumber k_j = kmin + j (kmax - kmin)/(nk - 1) (rad/m, k = omega/v).
+ * The paper designs the filters in advance as an optimization (Sec. II,
+ * Sec. III) but does not give the method; this library fits, per entry, the
+ * one-way phase shift over dz,
+ *     D(theta) = exp(+i zeta sqrt(kappa^2 - theta^2))    (theta <= kappa)
+ *     D(theta) = exp(-zeta sqrt(theta^2 - kappa^2))      (theta >  kappa)
+ * with kappa = k_j dx, zeta = dz/dx, theta = kx dx on a midpoint grid of
+ * `ngrid` points in (0, pi), by weighted least squares over even taps
+ * (H(theta) = h0 + 2 sum h_n cos(n theta)).  Initial weights: w_pass for
+ * theta <= kappa sin(theta_max), w_trans up to kappa, w_evan beyond.  Then
+ * `nreweight` passes multiply the weight of every point with |H| > 1 by
+ * (1 + beta (|H| - 1)/tau) and refit.  Finally the taps are scaled so that
+ * max |H| over an `ncheck`-point midpoint grid, divided by
+ * cos(M pi / (2 ncheck)), is at most 1 - margin; by Bernstein's inequality this
+ * bounds |H(theta)| for every theta.  `lambda` is added to the diagonal of the
+ * normal matrix.
+ */
+typedef struct {
+    int32_t ntaps;          /* N, odd, 1..MIG_MAX_NTAPS                       */
+    int32_t nk;             /* table entries, >= 2                            */
+    double kmin, kmax;      /* table axis, rad/m, 0 < kmin < kmax             */
+    double dx, dz;          /* m, dx > 0, dz >= 0                             */
+    double theta_max_deg;   /* passband half-angle (default 60)              */
+    double w_pass, w_trans, w_evan; /* > 0 (defaults 1, 0.01, 0.01)            */
+    int32_t ngrid;          /* design grid, 8..2048 (default 1024)            */
+    int32_t ncheck;         /* check grid, >= 8 (default 8192)                */
+    int32_t nreweight;      /* >= 0 (default 30)                              */
+    int32_t reserved;       /* must be 0                                      */
+    double lambda;          /* >= 0 (default 1e-9 * ngrid)                    */
+    double beta, tau;       /* reweighting gain and scale (defaults 1, 1e-4)  */
+    double margin;          /* stability margin in [0, 1) (default 1e-5)     */
+} mig_table_desc;
+
+/* Human-readable text for a status code (static storage). */
+MIG_API const char* mig_strerror(int code);
+
+/* Library version string (static storage). */
+MIG_API const char* mig_version(void);
+
+/* Bytes of workspace mig_design_table needs for this descriptor (0 on a bad
+ * descriptor). */
+MIG_API size_t mig_design_workspace_size(const mig_table_desc* d);
+
+/*
+ * A0 -- design the extrapolator table on the GPU in FP64 (the "predesigned
+ * 1-D FIR filters" of Algorithm 1; Sec. II/III: design as an optimization,
+ * accurate designs needed for stability; method as described above).
+ *   tab64   [nk][M+1] complex128 half-taps h_0..h_M (h_{-n} = h_n)   (out)
+ *   tab32   [nk][M+1] complex64, tab64 rounded to nearest, or NULL   (out)
+ *   maxgain [nk] max |H| over the check grid after scaling, or NULL  (out)
+ *   passerr [nk] max |H - D| over passband design-grid points, or NULL (out)
+ *   ws      >= mig_design_workspace_size(d) bytes of device memory
+ * Synchronizes `stream` and returns MIG_E_UNSTABLE if any entry's scaled
+ * maxgain is not <= 1 (e.g. NaN), MIG_E_ARG if the normal matrix of an entry
+ * is not positive definite.
+ */
+MIG_API int mig_design_table(const mig_table_desc* d, mig_c128* tab64,
+                             mig_c64* tab32, double* maxgain, double* passerr,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * A1 -- table look-up (Algorithm 1 "look-up table"; Sec. III filter chosen by
+ * the wavenumber omega/v).  idx[row][x][r] = nearest entry j to
+ * omega_r / vel[row][x], computed as the IEEE-double sequence
+ *     a = omega/dk; b = kmin/dk; s = 1/(double)v; t = a*s; t = t - b;
+ *     u = t + 0.5;  j = 0 if !(u >= 1), nk-1 if u >= nk, else floor(u),
+ * (dk = (kmax-kmin)/(nk-1), every operation rounded separately; j = 0 when
+ * v is not > 0).  The extrapolation kernels use exactly this rule.
+ *   vel [nrows][nx] float32, omega [nw] float64, idx [nrows][nx][nw] int32.
+ */
+MIG_API int mig_table_index(const float* vel, const double* omega,
+                            const mig_table_desc* d, int32_t nx, int32_t nw,
+                            int32_t nrows, int32_t* idx, void* stream);
+
+/* Bytes of workspace mig_extrapolate (with rows) and mig_migrate need to run
+ * all `nsteps` depth steps in one pass.  A smaller workspace (at least
+ * mig_workspace_min_size) makes the library split the depth loop into chunks. */
+MIG_API size_t mig_workspace_size(int32_t nx, int32_t nsteps, int32_t nw,
+                                  const mig_table_desc* d);
+MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw,
+                                      const mig_table_desc* d);
+
+/*
+ * A2 + A3 + A4 -- advance a plane by `nsteps` depth steps with Eq. (1) in FP32
+ * complex arithmetic, filters from `tab32` per output point (step s uses
+ * vel[s][.]; zero wavefield outside [0, nx)), optionally forming the image row
+ * of each new plane with FP64 accumulation over frequencies.
+ *   wf_in  [nx][nw] complex64 plane at z_k0                          (in)
+ *   wf_out [nx][nw] complex64 plane at z_k0+nsteps; must not overlap wf_in;
+ *          may be NULL when rows is non-NULL                           (out)
+ *   vel    [nsteps][nx] float32 propagation velocity                   (in)
+ *   omega  [nw] float64                                               (in)
+ *   tab32  [nk][M+1] complex64 half-taps (from mig_design_table)       (in)
+ *   rows   [nsteps][nx] float64: rows[s][x] = sum_r Re P_{k0+s+1}[x][r], or
+ *          NULL                                                        (out)
+ *   ws     workspace when rows != NULL (see mig_workspace_size); ignored
+ *          (may be NULL) when rows == NULL
+ * nsteps = 0 copies wf_in to wf_out.
+ */
+MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out,
+                            const float* vel, const double* omega,
+                            const mig_c64* tab32, const mig_table_desc* d,
+                            int32_t nx, int32_t nw, int32_t nsteps,
+                            double* rows, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * A3 -- image row of one plane (Algorithm 1 "depth row by summing over
+ * frequencies"): row[x] = sum_r Re wf[x][r], FP64 accumulation in a fixed
+ * order (one wavefront per x, lane-strided partial sums combined by a
+ * butterfly of cross-lane shuffles), so results are run-to-run identical.
+ *   wf [nx][nw] complex64 (in), row [nx] float64 (out).
+ */
+MIG_API int mig_image(const mig_c64* wf, double* row, int32_t nx, int32_t nw,
+                      void* stream);
+
+/*
+ * A0..A4 end to end -- Algorithm 1 on an f-x section: image row 0 is the
+ * image of `data`; row k (1 <= k < nz) is the image after k depth steps, step
+ * k-1 -> k using vel[k-1][.] (vel row nz-1 is not used).
+ *   data  [nx][nw] complex64 surface plane (in), vel [nz][nx] float32 (in),
+ *   omega [nw] float64 (in), tab32 [nk][M+1] complex64 (in),
+ *   image [nz][nx] float64 (out), ws >= mig_workspace_min_size bytes
+ *   (mig_workspace_size(nx, nz-1, nw, d) for a single pass).
+ */
+MIG_API int mig_migrate(const mig_c64* data, const float* vel,
+                        const double* omega, const mig_c64* tab32,
+                        const mig_table_desc* d, int32_t nx, int32_t nz,
+                        int32_t nw, double* image, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Diagnostic query: which extrapolation kernel a call with these sizes takes.
+ * 1 = register-tap kernel, two outputs per thread (N <= 35, nx <= 1024);
+ * 2 = register-tap kernel, four outputs per thread (N <= 35, nx <= 2048);
+ * 0 = general kernel (taps read from the table every step); -1 = bad
+ * arguments.  All kernels compute the same sums; results agree to FP32
+ * rounding. */
+MIG_API int mig_kernel_kind(int32_t nx, int32_t ntaps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIG_H */

@@ -1,0 +1,226 @@
+"""Python binding of libmig.so (C ABI in include/mig.h) over torch tensors.
+
+Argument marshalling only: shapes and dtypes are checked, device pointers and
+the current HIP stream are passed through, and every step of the method runs
+in the library's kernels.  The library must be built (``__graft_entry__.build``
+or ``python paper_1912_05529_amd/build.py``); if it is missing, every call
+raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmig.so")
+
+MIG_OK, MIG_E_ARG, MIG_E_UNSTABLE, MIG_E_DEVICE, MIG_E_WORKSPACE = 0, -1, -2, -3, -4
+
+_lib = None
+
+
+class MigError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+
+
+class CDesc(C.Structure):
+    """ctypes mirror of ``mig_table_desc``."""
+
+    _fields_ = [
+        ("ntaps", C.c_int32), ("nk", C.c_int32),
+        ("kmin", C.c_double), ("kmax", C.c_double),
+        ("dx", C.c_double), ("dz", C.c_double),
+        ("theta_max_deg", C.c_double),
+        ("w_pass", C.c_double), ("w_trans", C.c_double), ("w_evan", C.c_double),
+        ("ngrid", C.c_int32), ("ncheck", C.c_int32), ("nreweight", C.c_int32),
+        ("reserved", C.c_int32),
+        ("lambda_", C.c_double), ("beta", C.c_double), ("tau", C.c_double),
+        ("margin", C.c_double),
+    ]
+
+
+def cdesc(d) -> CDesc:
+    """Builds the C descriptor from any object with the TableDesc fields."""
+    lam = d.lam if getattr(d, "lam", None) is not None else 1e-9 * d.ngrid
+    return CDesc(int(d.ntaps), int(d.nk), float(d.kmin), float(d.kmax), float(d.dx),
+                 float(d.dz), float(d.theta_max_deg), float(d.w_pass), float(d.w_trans),
+                 float(d.w_evan), int(d.ngrid), int(d.ncheck), int(d.nreweight), 0,
+                 float(lam), float(d.beta), float(d.tau), float(d.margin))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmig.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    P, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    D = C.POINTER(CDesc)
+    sig = {
+        "mig_strerror": ([C.c_int], C.c_char_p),
+        "mig_version": ([], C.c_char_p),
+        "mig_design_workspace_size": ([D], sz),
+        "mig_design_table": ([D, P, P, P, P, P, sz, P], C.c_int),
+        "mig_table_index": ([P, P, D, i32, i32, i32, P, P], C.c_int),
+        "mig_workspace_size": ([i32, i32, i32, D], sz),
+        "mig_workspace_min_size": ([i32, i32, D], sz),
+        "mig_extrapolate": ([P, P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
+        "mig_image": ([P, P, i32, i32, P], C.c_int),
+        "mig_migrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
+        "mig_kernel_kind": ([i32, i32], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().mig_strerror(int(code)).decode()
+
+
+def version() -> str:
+    return lib().mig_version().decode()
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def _check(rc, what):
+    if rc != MIG_OK:
+        raise MigError(rc, what)
+
+
+def design_workspace_size(desc) -> int:
+    cd = cdesc(desc)
+    return int(lib().mig_design_workspace_size(C.byref(cd)))
+
+
+def design_table(desc, device="cuda", ws=None):
+    """A0: returns dict(tab64 [nk][M+1] complex128, tab32 complex64, maxgain, passerr)."""
+    cd = cdesc(desc)
+    K = (desc.ntaps - 1) // 2 + 1
+    dev = torch.device(device)
+    tab64 = torch.empty((desc.nk, K), dtype=torch.complex128, device=dev)
+    tab32 = torch.empty((desc.nk, K), dtype=torch.complex64, device=dev)
+    mg = torch.empty(desc.nk, dtype=torch.float64, device=dev)
+    pe = torch.empty(desc.nk, dtype=torch.float64, device=dev)
+    need = design_workspace_size(desc)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    rc = lib().mig_design_table(C.byref(cd), _p(tab64), _p(tab32), _p(mg), _p(pe), _p(ws),
+                                ws.numel(), _stream())
+    _check(rc, "mig_design_table")
+    return {"tab64": tab64, "tab32": tab32, "maxgain": mg, "passerr": pe}
+
+
+def table_index(vel, omega, desc):
+    """A1: vel [nrows][nx] float32, omega [nw] float64 -> int32 [nrows][nx][nw]."""
+    if vel.dim() == 1:
+        vel = vel[None]
+    nrows, nx = vel.shape
+    nw = omega.numel()
+    _need(vel, torch.float32, (nrows, nx), "vel")
+    _need(omega, torch.float64, (nw,), "omega")
+    idx = torch.empty((nrows, nx, nw), dtype=torch.int32, device=vel.device)
+    cd = cdesc(desc)
+    _check(lib().mig_table_index(_p(vel), _p(omega), C.byref(cd), nx, nw, nrows, _p(idx),
+                                 _stream()), "mig_table_index")
+    return idx
+
+
+def workspace_size(nx, nsteps, nw, desc) -> int:
+    cd = cdesc(desc)
+    return int(lib().mig_workspace_size(nx, nsteps, nw, C.byref(cd)))
+
+
+def workspace_min_size(nx, nw, desc) -> int:
+    cd = cdesc(desc)
+    return int(lib().mig_workspace_min_size(nx, nw, C.byref(cd)))
+
+
+def kernel_kind(nx, ntaps) -> int:
+    return int(lib().mig_kernel_kind(nx, ntaps))
+
+
+def extrapolate(wf, vel, omega, tab32, desc, nsteps=None, rows=True, out=None, ws=None,
+                want_plane=True):
+    """A2-A4: advance wf [nx][nw] complex64 by nsteps (default vel.shape[0]).
+
+    Returns (plane or None, rows [nsteps][nx] float64 or None)."""
+    nx, nw = wf.shape
+    if nsteps is None:
+        nsteps = vel.shape[0]
+    _need(wf, torch.complex64, (nx, nw), "wf")
+    if vel.shape[0] < nsteps or vel.shape[1] != nx:
+        raise ValueError("vel must have at least nsteps rows of nx")
+    _need(vel, torch.float32, None, "vel")
+    _need(omega, torch.float64, (nw,), "omega")
+    _need(tab32, torch.complex64, (desc.nk, (desc.ntaps - 1) // 2 + 1), "tab32")
+    if want_plane and out is None:
+        out = torch.empty_like(wf)
+    if out is not None:
+        _need(out, torch.complex64, (nx, nw), "out")
+    rws = torch.empty((nsteps, nx), dtype=torch.float64, device=wf.device) if rows else None
+    if rows and ws is None:
+        ws = torch.empty(max(workspace_size(nx, nsteps, nw, desc), 1), dtype=torch.uint8,
+                         device=wf.device)
+    cd = cdesc(desc)
+    rc = lib().mig_extrapolate(_p(wf), _p(out), _p(vel), _p(omega), _p(tab32), C.byref(cd),
+                               nx, nw, nsteps, _p(rws), _p(ws), 0 if ws is None else ws.numel(),
+                               _stream())
+    _check(rc, "mig_extrapolate")
+    return out, rws
+
+
+def image(wf):
+    """A3: row[x] = sum_r Re wf[x][r] (float64)."""
+    nx, nw = wf.shape
+    _need(wf, torch.complex64, (nx, nw), "wf")
+    row = torch.empty(nx, dtype=torch.float64, device=wf.device)
+    _check(lib().mig_image(_p(wf), _p(row), nx, nw, _stream()), "mig_image")
+    return row
+
+
+def migrate(data, vel, omega, tab32, desc, ws=None, out=None):
+    """Algorithm 1 end to end: data [nx][nw] complex64, vel [nz][nx] -> image [nz][nx]."""
+    nx, nw = data.shape
+    nz = vel.shape[0]
+    _need(data, torch.complex64, (nx, nw), "data")
+    _need(vel, torch.float32, (nz, nx), "vel")
+    _need(omega, torch.float64, (nw,), "omega")
+    _need(tab32, torch.complex64, (desc.nk, (desc.ntaps - 1) // 2 + 1), "tab32")
+    if ws is None:
+        ws = torch.empty(max(workspace_size(nx, max(nz - 1, 1), nw, desc), 1),
+                         dtype=torch.uint8, device=data.device)
+    img = out if out is not None else torch.empty((nz, nx), dtype=torch.float64,
+                                                  device=data.device)
+    _need(img, torch.float64, (nz, nx), "image")
+    cd = cdesc(desc)
+    rc = lib().mig_migrate(_p(data), _p(vel), _p(omega), _p(tab32), C.byref(cd), nx, nz, nw,
+                           _p(img), _p(ws), ws.numel(), _stream())
+    _check(rc, "mig_migrate")
+    return img

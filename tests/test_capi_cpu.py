@@ -1,0 +1,90 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/mig.h declares, and rejects bad arguments on the host before launching."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mig.h")).read()
+    return sorted(set(re.findall(r"MIG_API[^;(]*?\b(mig_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1912_05529_amd import mig
+    return mig.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror_and_version(L):
+    from paper_1912_05529_amd import mig
+    assert mig.strerror(0) == "success"
+    assert "argument" in mig.strerror(-1)
+    assert "gfx950" in mig.version()
+
+
+def _desc(**kw):
+    from paper_1912_05529_amd import synth
+    base = dict(ntaps=25, nk=64, kmin=0.01, kmax=0.4, dx=10.0, dz=10.0)
+    base.update(kw)
+    return synth.TableDesc(**base)
+
+
+def test_host_validation_rejects_bad_arguments(L):
+    from paper_1912_05529_amd import mig
+    fake = C.c_void_p(4096)
+    good = mig.cdesc(_desc())
+    # NULL descriptor, even N, inverted table range, NULL plane
+    assert L.mig_extrapolate(fake, fake, fake, fake, fake, None, 8, 2, 1, None, None, 0, None) == -1
+    even = mig.cdesc(_desc(ntaps=24))
+    assert L.mig_extrapolate(fake, C.c_void_p(8192), fake, fake, fake, C.byref(even), 8, 2, 1,
+                             None, None, 0, None) == -1
+    inv = mig.cdesc(_desc(kmin=0.5, kmax=0.1))
+    assert L.mig_migrate(fake, fake, fake, fake, C.byref(inv), 8, 4, 2, fake, fake, 1 << 20,
+                         None) == -1
+    assert L.mig_extrapolate(None, fake, fake, fake, fake, C.byref(good), 8, 2, 1, None, None, 0,
+                             None) == -1
+    # aliasing planes
+    assert L.mig_extrapolate(fake, C.c_void_p(4096 + 8), fake, fake, fake, C.byref(good), 8, 2,
+                             1, None, None, 0, None) == -1
+    # sizes out of range
+    assert L.mig_image(fake, fake, 0, 4, None) == -1
+    assert L.mig_image(fake, fake, 8193, 4, None) == -1
+    # rows requested without workspace
+    assert L.mig_extrapolate(fake, C.c_void_p(1 << 30), fake, fake, fake, C.byref(good), 8, 2, 3,
+                             fake, None, 0, None) == -4
+    # design descriptor checks (zero weight breaks reweighting; ngrid too large)
+    bad = mig.cdesc(_desc(w_trans=0.0))
+    assert L.mig_design_workspace_size(C.byref(bad)) == 0
+    assert L.mig_design_table(C.byref(bad), fake, None, None, None, fake, 1 << 20, None) == -1
+    big = mig.cdesc(_desc(ngrid=4096))
+    assert L.mig_design_table(C.byref(big), fake, None, None, None, fake, 1 << 30, None) == -1
+    small = mig.cdesc(_desc())
+    assert L.mig_design_table(C.byref(small), fake, None, None, None, fake, 16, None) == -4
+
+
+def test_workspace_sizes_and_kernel_kinds(L):
+    from paper_1912_05529_amd import mig
+    d = _desc(ntaps=35, nk=2048)
+    full = mig.workspace_size(1024, 511, 200, d)
+    one = mig.workspace_min_size(1024, 200, d)
+    plane = 1024 * 200 * 8
+    assert one == plane + 200 * 1024 * 4
+    assert full == plane + 511 * 200 * 1024 * 4
+    assert mig.kernel_kind(1024, 35) == 1
+    assert mig.kernel_kind(1025, 35) == 2
+    assert mig.kernel_kind(2048, 25) == 2
+    assert mig.kernel_kind(2049, 25) == 0
+    assert mig.kernel_kind(512, 37) == 0
+    assert mig.kernel_kind(512, 36) == -1

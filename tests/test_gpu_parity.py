@@ -1,0 +1,170 @@
+"""GPU parity against the FP64 oracle, through the C ABI (libmig.so).
+
+Tolerances
+  * table design (FP64 on both sides, same formulas, same accumulation order;
+    only libm vs device cos/sin/exp/hypot differ in the last bit): 1e-10
+    relative to the largest tap;
+  * table look-up: bit-exact (same IEEE-double operation sequence);
+  * FP32 extrapolation vs FP64 oracle: relative L2 <= 1e-5 after a few steps
+    (FP32 taps and arithmetic, ~1e-7 per operation, ~2N operations per output
+    per step), and relative image L2 <= 1e-4 over a full section (the target);
+  * imaging of the same complex64 plane: FP64 sums in a different order,
+    1e-13 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1912_05529_amd import mig, synth
+from gpu_helpers import data64, dev, rel_l2, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tables():
+    cache = {}
+
+    def get(desc):
+        if desc not in cache:
+            cache[desc] = (oracle.design_table(desc), mig.design_table(desc, dev()))
+        return cache[desc]
+    return get
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+def test_design_table_matches_oracle(which, tables, cfg1, cfg2_model):
+    desc = (cfg1 if which == "cfg1" else cfg2_model).desc
+    (ot, omg, ope, _), g = tables(desc)
+    t64 = g["tab64"].cpu().numpy()
+    err = np.abs(t64 - ot).max() / np.abs(ot).max()
+    print("%s table max rel diff %.3e" % (which, err))
+    assert err <= 1e-10
+    assert np.abs(g["maxgain"].cpu().numpy() - omg).max() <= 1e-10
+    assert np.abs(g["passerr"].cpu().numpy() - ope).max() <= 1e-10
+    assert float(g["maxgain"].max()) <= 1.0
+    assert torch.equal(g["tab32"], g["tab64"].to(torch.complex64))
+
+
+def test_table_index_bit_exact(cfg2_model):
+    desc = cfg2_model.desc
+    rng = np.random.default_rng(4)
+    vel = rng.uniform(700.0, 2500.0, (5, 300)).astype(np.float32)
+    vel[0, :7] = [0.0, -0.0, -3.0, np.nan, np.inf, 1e-30, 3e38]
+    vel[1] = cfg2_model.vel[100, :300]
+    om = cfg2_model.omega
+    ref = oracle.table_index(desc, om, vel)
+    got = mig.table_index(torch.from_numpy(vel).to(dev()), torch.from_numpy(om).to(dev()), desc)
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
+CASES = [
+    # nx, nw, nsteps, ntaps, layered velocity
+    (64, 8, 7, 25, True),
+    (100, 5, 6, 35, False),
+    (1000, 4, 5, 35, True),
+    (1024, 3, 4, 35, False),
+    (1025, 3, 4, 35, True),
+    (1500, 2, 5, 25, False),
+    (2048, 2, 3, 35, True),
+    (2049, 2, 3, 35, False),
+    (300, 3, 4, 37, False),
+    (1, 2, 3, 25, False),
+    (2, 1, 2, 35, False),
+    (129, 3, 1, 1, False),
+    (77, 2, 2, 3, True),
+]
+
+
+@pytest.mark.parametrize("nx,nw,nsteps,ntaps,layered", CASES)
+def test_extrapolate_matches_oracle(nx, nw, nsteps, ntaps, layered, tables):
+    sec = synth.random_case(1000 + nx + ntaps, nx, nsteps + 1, nw, ntaps=ntaps, nk=256,
+                            layered=layered)
+    (ot, _, _, _), g = tables(sec.desc)
+    print("case nx=%d nw=%d nsteps=%d N=%d kind=%d" % (nx, nw, nsteps, ntaps,
+                                                       mig.kernel_kind(nx, ntaps)), flush=True)
+    t = upload(sec)
+    vel = t["vel"][:nsteps].contiguous()
+    plane, rows = mig.extrapolate(t["data"], vel, t["omega"], g["tab32"], sec.desc, nsteps)
+    torch.cuda.synchronize()
+    ref_plane, ref_rows = oracle.extrapolate(sec.desc, ot, sec.omega, sec.vel[:nsteps],
+                                             data64(sec), nsteps)
+    p = plane.cpu().numpy()
+    assert rel_l2(p, ref_plane) <= 1e-5
+    assert np.abs(p - ref_plane).max() <= 1e-4 * np.abs(ref_plane).max()
+    assert rel_l2(rows.cpu().numpy(), ref_rows) <= 1e-5
+    # rows off: same plane bit for bit
+    plane2, none = mig.extrapolate(t["data"], vel, t["omega"], g["tab32"], sec.desc, nsteps,
+                                   rows=False)
+    assert none is None and torch.equal(plane2, plane)
+
+
+def test_image_matches_oracle():
+    rng = np.random.default_rng(8)
+    for nx, nw in [(1, 1), (7, 300), (130, 64), (1024, 200)]:
+        P = (rng.standard_normal((nx, nw)) + 1j * rng.standard_normal((nx, nw))).astype(np.complex64)
+        row = mig.image(torch.from_numpy(P).to(dev())).cpu().numpy()
+        ref = oracle.image(P.astype(np.complex128))
+        assert np.abs(row - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1.0)
+
+
+def test_migrate_config1_matches_oracle_and_focuses(cfg1, cfg1_table, tables):
+    g = tables(cfg1.desc)[1]
+    t = upload(cfg1)
+    img = mig.migrate(t["data"], t["vel"], t["omega"], g["tab32"], cfg1.desc).cpu().numpy()
+    ref = oracle.migrate(cfg1.desc, cfg1_table[0], cfg1.omega, cfg1.vel, data64(cfg1))
+    err = rel_l2(img, ref)
+    print("config1 image rel L2 %.3e" % err)
+    assert err <= 1e-4
+    iz, ix = np.unravel_index(np.argmax(np.abs(img)), img.shape)
+    assert abs(iz - cfg1.extra["iz0"]) <= 1 and abs(ix - cfg1.extra["ix0"]) <= 1
+
+
+@pytest.fixture(scope="module")
+def cfg2_full():
+    return synth.config2()
+
+
+def test_migrate_config2_full_matches_oracle(cfg2_full, tables):
+    sec = cfg2_full
+    (ot, _, _, _), g = tables(sec.desc)
+    t = upload(sec)
+    img = mig.migrate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc).cpu().numpy()
+    ref = oracle.migrate(sec.desc, ot, sec.omega, sec.vel, data64(sec))
+    err = rel_l2(img, ref)
+    rows = [rel_l2(img[k], ref[k]) for k in (1, 128, 256, 511)]
+    print("config2 image rel L2 %.3e; rows 1/128/256/511: %s" % (err, rows))
+    assert err <= 1e-4
+
+
+def test_migrate_is_deterministic_and_chunking_is_exact(tables):
+    sec = synth.random_case(77, 300, 40, 24, ntaps=35, nk=256)
+    g = tables(sec.desc)[1]
+    t = upload(sec)
+    args = (t["data"], t["vel"], t["omega"], g["tab32"], sec.desc)
+    a = mig.migrate(*args)
+    b = mig.migrate(*args)
+    assert torch.equal(a, b)
+    for nbytes in (mig.workspace_min_size(300, 24, sec.desc),
+                   mig.workspace_min_size(300, 24, sec.desc) + 7 * 24 * 320 * 4 + 5):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev())
+        c = mig.migrate(*args, ws=ws)
+        assert torch.equal(a, c)
+
+
+def test_extrapolate_zero_steps_and_errors(tables):
+    sec = synth.random_case(5, 50, 3, 4, ntaps=25, nk=64)
+    g = tables(sec.desc)[1]
+    t = upload(sec)
+    out, _ = mig.extrapolate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc, 0,
+                             rows=False)
+    assert torch.equal(out, t["data"])
+    with pytest.raises(mig.MigError) as e:
+        mig.extrapolate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc, 2, rows=False,
+                        out=t["data"])
+    assert e.value.code == mig.MIG_E_ARG
+    small = torch.empty(16, dtype=torch.uint8, device=dev())
+    with pytest.raises(mig.MigError) as e:
+        mig.extrapolate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc, 2, ws=small)
+    assert e.value.code == mig.MIG_E_WORKSPACE
