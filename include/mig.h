@@ -143,9 +143,10 @@ MIG_API int mig_table_index(const float* vel, const double* omega,
                             const mig_table_desc* d, int32_t nx, int32_t nw,
                             int32_t nrows, int32_t* idx, void* stream);
 
-/* Bytes of workspace mig_extrapolate (with rows) and mig_migrate need to run
- * all `nsteps` depth steps in one pass.  A smaller workspace (at least
- * mig_workspace_min_size) makes the library split the depth loop into chunks. */
+/* Bytes of workspace mig_extrapolate (with or without rows) and mig_migrate
+ * need to run all `nsteps` depth steps in one launch.  A smaller workspace (at
+ * least mig_workspace_min_size) makes the library split the depth loop into
+ * chunks of as many steps as fit; results are bit-identical. */
 MIG_API size_t mig_workspace_size(int32_t nx, int32_t nsteps, int32_t nw,
                                   const mig_table_desc* d);
 MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw,
@@ -164,9 +165,12 @@ MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw,
  *   tab32  [nk][M+1] complex64 half-taps (from mig_design_table)       (in)
  *   rows   [nsteps][nx] float64: rows[s][x] = sum_r Re P_{k0+s+1}[x][r], or
  *          NULL                                                        (out)
- *   ws     workspace when rows != NULL (see mig_workspace_size); ignored
- *          (may be NULL) when rows == NULL
- * nsteps = 0 copies wf_in to wf_out.
+ *   ws     device workspace, >= mig_workspace_min_size bytes
+ *          (mig_workspace_size(nx, nsteps, nw, d) for a single pass); it
+ *          holds the slowness rows 1/v of the look-up, the partial image rows
+ *          and, when the depth loop is split into chunks, the intermediate
+ *          plane.  Must not overlap wf_in or wf_out.
+ * nsteps = 0 copies wf_in to wf_out (ws unused).
  */
 MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out,
                             const float* vel, const double* omega,

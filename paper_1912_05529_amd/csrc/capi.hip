@@ -44,34 +44,45 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb)
 
 size_t plane_bytes(int nx, int nw) { return align_up((size_t)nx * nw * sizeof(float2), kAlign); }
 
-int ldp_of(int nx) { return (nx + 63) / 64 * 64; }
-
-size_t part_step_bytes(int nx, int nw) { return (size_t)nw * ldp_of(nx) * sizeof(float); }
+// Workspace per depth step: one slowness row (+ one partial-row plane when
+// image rows are formed).
+size_t step_bytes(int nx, int nw, bool rows)
+{
+    size_t b = (size_t)row_stride(nx) * sizeof(double);
+    if (rows) b += (size_t)nw * row_stride(nx) * sizeof(float);
+    return b;
+}
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
-// Depth loop with image rows, split into chunks that fit the workspace.
-int run_extrap_rows(const float2* src, float2* dst, const float* vel, const double* omega,
-                    const float2* tab, const mig_table_desc* d, int nx, int nw, int nsteps,
-                    double* rows, void* ws, size_t ws_bytes, hipStream_t s)
+// Depth loop, split into chunks that fit the workspace.  Workspace layout:
+// [scratch plane][slowness chunk x ldp doubles][partials chunk x nw x ldp floats].
+int run_extrap(const float2* src, float2* dst, const float* vel, const double* omega,
+               const float2* tab, const mig_table_desc* d, int nx, int nw, int nsteps,
+               double* rows, void* ws, size_t ws_bytes, hipStream_t s)
 {
     const size_t pb = plane_bytes(nx, nw);
-    const size_t sb = part_step_bytes(nx, nw);
+    const size_t sb = step_bytes(nx, nw, rows != nullptr);
     if (!ws || ws_bytes < pb + sb) return MIG_E_WORKSPACE;
-    float2* scratch = static_cast<float2*>(ws);
-    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + pb);
     size_t fit = (ws_bytes - pb) / sb;
-    int chunk = fit >= (size_t)nsteps ? nsteps : (int)fit;
+    const int chunk = fit >= (size_t)nsteps ? nsteps : (int)fit;
+    const int ldp = row_stride(nx);
+    // ldp is a multiple of 256, so every region below starts 2 KB-aligned.
+    float2* scratch = static_cast<float2*>(ws);
+    double* slow = reinterpret_cast<double*>(static_cast<char*>(ws) + pb);
+    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + pb +
+                                           (size_t)chunk * ldp * sizeof(double));
 
     ExtrapArgs a;
     a.omega = omega;
     a.tab = tab;
-    a.part = part;
+    a.slow = slow;
+    a.part = rows ? part : nullptr;
     a.nx = nx;
     a.nw = nw;
     a.nk = d->nk;
     a.M = (d->ntaps - 1) / 2;
-    a.ldp = ldp_of(nx);
+    a.ldp = ldp;
     a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
     a.b = d->kmin / a.dk;
 
@@ -79,16 +90,19 @@ int run_extrap_rows(const float2* src, float2* dst, const float* vel, const doub
     for (int c0 = 0; c0 < nsteps; c0 += chunk) {
         int cs = nsteps - c0 < chunk ? nsteps - c0 : chunk;
         bool last = c0 + cs == nsteps;
+        int rc = launch_slowness(vel + (size_t)c0 * nx, nx, cs, ldp, slow, s);
+        if (rc != MIG_OK) return rc;
         a.win = cur;
         // Intermediate planes go to the scratch plane, in place: each workgroup
         // reads its whole frequency column before writing it back.
         a.wout = last ? dst : scratch;
-        a.vel = vel + (size_t)c0 * nx;
         a.nsteps = cs;
-        int rc = launch_extrap(a, s);
+        rc = launch_extrap(a, s);
         if (rc != MIG_OK) return rc;
-        rc = launch_rows_reduce(part, a.ldp, nx, nw, cs, rows + (size_t)c0 * nx, s);
-        if (rc != MIG_OK) return rc;
+        if (rows) {
+            rc = launch_rows_reduce(part, ldp, nx, nw, cs, rows + (size_t)c0 * nx, s);
+            if (rc != MIG_OK) return rc;
+        }
         cur = scratch;
     }
     return MIG_OK;
@@ -173,13 +187,13 @@ MIG_API size_t mig_workspace_size(int32_t nx, int32_t nsteps, int32_t nw, const 
 {
     if (!desc_valid(d) || !sizes_ok(nx, nw) || nsteps < 0) return 0;
     size_t steps = nsteps > 0 ? (size_t)nsteps : 1;
-    return plane_bytes(nx, nw) + steps * part_step_bytes(nx, nw);
+    return plane_bytes(nx, nw) + steps * step_bytes(nx, nw, true);
 }
 
 MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw, const mig_table_desc* d)
 {
     if (!desc_valid(d) || !sizes_ok(nx, nw)) return 0;
-    return plane_bytes(nx, nw) + part_step_bytes(nx, nw);
+    return plane_bytes(nx, nw) + step_bytes(nx, nw, true);
 }
 
 MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out, const float* vel,
@@ -200,27 +214,10 @@ MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out, const float* 
             return MIG_E_DEVICE;
         return MIG_OK;
     }
-    if (rows) {
-        if (ws && overlap(ws, ws_bytes, wf_in, pl)) return MIG_E_ARG;
-        return run_extrap_rows(src, dst, vel, omega, reinterpret_cast<const float2*>(tab32), d,
-                               nx, nw, nsteps, rows, ws, ws_bytes, s);
-    }
-    ExtrapArgs a;
-    a.win = src;
-    a.wout = dst;
-    a.vel = vel;
-    a.omega = omega;
-    a.tab = reinterpret_cast<const float2*>(tab32);
-    a.part = nullptr;
-    a.nx = nx;
-    a.nw = nw;
-    a.nsteps = nsteps;
-    a.nk = d->nk;
-    a.M = (d->ntaps - 1) / 2;
-    a.ldp = ldp_of(nx);
-    a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
-    a.b = d->kmin / a.dk;
-    return launch_extrap(a, s);
+    if (ws && (overlap(ws, ws_bytes, wf_in, pl) || (wf_out && overlap(ws, ws_bytes, wf_out, pl))))
+        return MIG_E_ARG;
+    return run_extrap(src, dst, vel, omega, reinterpret_cast<const float2*>(tab32), d, nx, nw,
+                      nsteps, rows, ws, ws_bytes, s);
 }
 
 MIG_API int mig_image(const mig_c64* wf, double* row, int32_t nx, int32_t nw, void* stream)
@@ -241,9 +238,9 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel, const double* ome
     if (rc != MIG_OK || nz == 1) return rc;
     const size_t pl = (size_t)nx * nw * sizeof(mig_c64);
     if (ws && overlap(ws, ws_bytes, data, pl)) return MIG_E_ARG;
-    return run_extrap_rows(reinterpret_cast<const float2*>(data), nullptr, vel, omega,
-                           reinterpret_cast<const float2*>(tab32), d, nx, nw, nz - 1, image + nx,
-                           ws, ws_bytes, s);
+    return run_extrap(reinterpret_cast<const float2*>(data), nullptr, vel, omega,
+                      reinterpret_cast<const float2*>(tab32), d, nx, nw, nz - 1, image + nx, ws,
+                      ws_bytes, s);
 }
 
 // Internal query used by tests and the benchmark: which extrapolation kernel

@@ -9,22 +9,33 @@
 //     synchronization" the paper names as future work, Sec. V), and there is no
 //     inter-workgroup traffic at all.
 //   * Lanes run along x (coalesced, conflict-free LDS windows); each thread
-//     owns two adjacent outputs and reads its 2M+2-point window with 16-byte LDS
+//     owns two (or four) adjacent outputs and reads its window with 16-byte LDS
 //     loads.  Even taps are folded: h_n (u[x-n] + u[x+n]).
 //   * Taps live in registers.  The filter of an output only changes when the
-//     velocity under it changes (ω is fixed per workgroup), which in layered
+//     velocity under it changes (omega is fixed per workgroup), which in layered
 //     media is a few times per column.  Two register sets alternate between
 //     even and odd steps; the set for step k+1 is refilled during step k only
-//     for outputs whose velocity changed, so table reads (L2-resident) are
-//     rare and their latency is hidden behind a full step of arithmetic.
+//     for outputs whose slowness changed, so table reads (L2-resident) are rare
+//     and their latency is hidden behind a full step of arithmetic.
+//   * The look-up needs 1/v in FP64; it is computed once per (depth, x) by a
+//     small pre-pass (shared by all frequencies) instead of once per refill.
 //   * The image row needs a sum over frequencies, i.e. across workgroups.
 //     Each workgroup writes Re of its new plane (float32, exact) to a partial
-//     buffer [step][ω][x]; a second kernel sums over ω in a fixed order in
-//     FP64, so images are run-to-run identical.
+//     buffer [step][omega][x]; a second kernel sums over omega in a fixed order
+//     in FP64, so images are run-to-run identical.
 #include "common.hpp"
 
 namespace mig {
 namespace {
+
+// s_waitcnt vmcnt(N) with the other counters left alone (GFX9 encoding:
+// vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] in bits 15:14).
+template <int N>
+__device__ __forceinline__ void wait_vmem()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
 
 __device__ __forceinline__ float2 cmulf(float2 h, float2 u)
 {
@@ -45,6 +56,11 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b)
     return make_float2(a.x + b.x, a.y + b.y);
 }
 
+__device__ __forceinline__ unsigned long long dbits(double d)
+{
+    return (unsigned long long)__double_as_longlong(d);
+}
+
 template <int M>
 __device__ __forceinline__ void load_taps(float2 (&h)[M + 1], const float2* __restrict__ row)
 {
@@ -54,10 +70,8 @@ __device__ __forceinline__ void load_taps(float2 (&h)[M + 1], const float2* __re
 
 // Two outputs x0, x0+1 from the window w[i] = P[x0 - M + i], i = 0..2M+1.
 template <int M>
-__device__ __forceinline__ void fir2(const float2* __restrict__ win,
-                                     const float2 (&h0)[M + 1],
-                                     const float2 (&h1)[M + 1], float2& o0,
-                                     float2& o1)
+__device__ __forceinline__ void fir2(const float2* __restrict__ win, const float2 (&h0)[M + 1],
+                                     const float2 (&h1)[M + 1], float2& o0, float2& o1)
 {
     float2 w[2 * M + 2];
     const float4* w4 = reinterpret_cast<const float4*>(win);
@@ -76,110 +90,6 @@ __device__ __forceinline__ void fir2(const float2* __restrict__ win,
     }
     o0 = a0;
     o1 = a1;
-}
-
-struct Lane {
-    int t, x0, xc0, xc1, LB, r;
-    bool ok0, ok1;
-    double ar;
-};
-
-// One depth step k with the current tap set; refills the other set for step
-// k+1 where the velocity changed, and prefetches the velocities of step k+2.
-template <int M>
-__device__ __forceinline__ void step_fast(const ExtrapArgs& a, float2* sm, const Lane& L,
-                                          int k, float2 (&hc)[2][M + 1],
-                                          float2 (&ho)[2][M + 1], unsigned (&bo)[2],
-                                          float& vn0, float& vn1, float2& o0, float2& o1)
-{
-    if (k >= 1 && k + 1 < a.nsteps) {
-        unsigned u0 = __float_as_uint(vn0), u1 = __float_as_uint(vn1);
-        if (u0 != bo[0]) {
-            bo[0] = u0;
-            load_taps<M>(ho[0], a.tab + (size_t)table_index(L.ar, a.b, a.nk, vn0) * (M + 1));
-        }
-        if (u1 != bo[1]) {
-            bo[1] = u1;
-            load_taps<M>(ho[1], a.tab + (size_t)table_index(L.ar, a.b, a.nk, vn1) * (M + 1));
-        }
-    }
-    float p0 = 0.0f, p1 = 0.0f;
-    if (k + 2 < a.nsteps) {
-        const float* vr = a.vel + (size_t)(k + 2) * a.nx;
-        p0 = vr[L.xc0];
-        p1 = vr[L.xc1];
-    }
-    fir2<M>(sm + (k & 1) * L.LB + 2 * L.t, hc[0], hc[1], o0, o1);
-    float2* dst = sm + ((k + 1) & 1) * L.LB + M + L.x0;
-    if (L.ok0) dst[0] = o0;
-    if (L.ok1) dst[1] = o1;
-    if (a.part) {
-        float* pr = a.part + ((size_t)k * a.nw + L.r) * a.ldp + L.x0;
-        if (L.ok1) *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
-        else if (L.ok0) pr[0] = o0.x;
-    }
-    vn0 = p0;
-    vn1 = p1;
-    __syncthreads();
-}
-
-// Register-tap kernel.  Block = ceil(nx/2) threads rounded up to a wavefront;
-// LDS = two planes of 2*blockDim + 2M + 2 points, P[x] at offset M + x, zero
-// elsewhere (the zero boundary of Eq. 1).
-template <int M>
-__global__ void __launch_bounds__(512) k_extrap_fast(ExtrapArgs a)
-{
-    extern __shared__ float4 smem4[];
-    float2* sm = reinterpret_cast<float2*>(smem4);
-    Lane L;
-    L.t = threadIdx.x;
-    L.r = blockIdx.x;
-    L.LB = 2 * blockDim.x + 2 * M + 2;
-    L.x0 = 2 * L.t;
-    L.ok0 = L.x0 < a.nx;
-    L.ok1 = L.x0 + 1 < a.nx;
-    L.xc0 = L.ok0 ? L.x0 : a.nx - 1;
-    L.xc1 = L.ok1 ? L.x0 + 1 : a.nx - 1;
-    L.ar = a.omega[L.r] / a.dk;
-
-    for (int i = L.t; i < 2 * L.LB; i += blockDim.x) sm[i] = make_float2(0.0f, 0.0f);
-    __syncthreads();
-    if (L.ok0) sm[M + L.x0] = a.win[(size_t)L.x0 * a.nw + L.r];
-    if (L.ok1) sm[M + L.x0 + 1] = a.win[(size_t)(L.x0 + 1) * a.nw + L.r];
-
-    float2 hA[2][M + 1], hB[2][M + 1];
-    unsigned bA[2], bB[2];
-    {
-        float v0 = a.vel[L.xc0], v1 = a.vel[L.xc1];
-        bA[0] = __float_as_uint(v0);
-        bA[1] = __float_as_uint(v1);
-        load_taps<M>(hA[0], a.tab + (size_t)table_index(L.ar, a.b, a.nk, v0) * (M + 1));
-        load_taps<M>(hA[1], a.tab + (size_t)table_index(L.ar, a.b, a.nk, v1) * (M + 1));
-    }
-    if (a.nsteps > 1) {
-        float v0 = a.vel[a.nx + L.xc0], v1 = a.vel[a.nx + L.xc1];
-        bB[0] = __float_as_uint(v0);
-        bB[1] = __float_as_uint(v1);
-        load_taps<M>(hB[0], a.tab + (size_t)table_index(L.ar, a.b, a.nk, v0) * (M + 1));
-        load_taps<M>(hB[1], a.tab + (size_t)table_index(L.ar, a.b, a.nk, v1) * (M + 1));
-    } else {
-        bB[0] = bB[1] = 0u;
-#pragma unroll
-        for (int n = 0; n <= M; ++n) hB[0][n] = hB[1][n] = make_float2(0.0f, 0.0f);
-    }
-    float vn0 = 0.0f, vn1 = 0.0f;
-    __syncthreads();
-
-    float2 o0 = make_float2(0.0f, 0.0f), o1 = o0;
-    for (int k = 0; k < a.nsteps; k += 2) {
-        step_fast<M>(a, sm, L, k, hA, hB, bB, vn0, vn1, o0, o1);
-        if (k + 1 >= a.nsteps) break;
-        step_fast<M>(a, sm, L, k + 1, hB, hA, bA, vn0, vn1, o0, o1);
-    }
-    if (a.wout) {
-        if (L.ok0) a.wout[(size_t)L.x0 * a.nw + L.r] = o0;
-        if (L.ok1) a.wout[(size_t)(L.x0 + 1) * a.nw + L.r] = o1;
-    }
 }
 
 // Four outputs x0..x0+3 from the window w[i] = P[x0 - M + i], i = 0..2M+3.
@@ -204,12 +114,122 @@ __device__ __forceinline__ void fir4(const float2* __restrict__ win, const float
     }
 }
 
+// slow[k][x] = slowness_of(vel[k][min(x, nx-1)]) for x < ldp.
+__global__ void k_slowness(const float* __restrict__ vel, int nx, int nrows, int ldp,
+                           double* __restrict__ slow)
+{
+    const size_t total = (size_t)nrows * ldp;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        size_t k = e / ldp;
+        int x = (int)(e % ldp);
+        slow[e] = slowness_of(vel[k * nx + (x < nx ? x : nx - 1)]);
+    }
+}
+
+struct Lane {
+    int t, x0, LB, r;
+    bool ok0, ok1;
+    double ar;
+};
+
+// One depth step k: wait for this step's taps (issued during step k-1),
+// refill the other set for step k+1 where the slowness changed, prefetch the
+// slowness of step k+2, then the folded FIR, LDS write and partial row.
+// VMEM operations of a step are issued in a fixed order -- [refills], one
+// slowness load, [one partial-row store] -- so the wait at the top of the
+// next step has a static count that never includes that step's refills.
+template <int M, bool ROWS>
+__device__ __forceinline__ void step_fast(const ExtrapArgs& a, float2* sm, const Lane& L, int k,
+                                          float2 (&hc)[2][M + 1], float2 (&ho)[2][M + 1],
+                                          unsigned long long (&bo)[2], double2& sn, float2& o0,
+                                          float2& o1)
+{
+    wait_vmem<ROWS ? 1 : 0>();
+    if (k >= 1 && k + 1 < a.nsteps) {
+        unsigned long long u0 = dbits(sn.x), u1 = dbits(sn.y);
+        if (u0 != bo[0]) {
+            bo[0] = u0;
+            load_taps<M>(ho[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, sn.x) * (M + 1));
+        }
+        if (u1 != bo[1]) {
+            bo[1] = u1;
+            load_taps<M>(ho[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, sn.y) * (M + 1));
+        }
+    }
+    const int kp = k + 2 < a.nsteps ? k + 2 : a.nsteps - 1;
+    const double2 p = *reinterpret_cast<const double2*>(a.slow + (size_t)kp * a.ldp + L.x0);
+    fir2<M>(sm + (k & 1) * L.LB + 2 * L.t, hc[0], hc[1], o0, o1);
+    float2* dst = sm + ((k + 1) & 1) * L.LB + M + L.x0;
+    if (L.ok0) dst[0] = o0;
+    if (L.ok1) dst[1] = o1;
+    if (ROWS) {
+        float* pr = a.part + ((size_t)k * a.nw + L.r) * a.ldp + L.x0;
+        *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
+    }
+    sn = p;
+    __syncthreads();
+}
+
+// Register-tap kernel.  Block = ceil(nx/2) threads rounded up to a wavefront;
+// LDS = two planes of 2*blockDim + 2M + 2 points, P[x] at offset M + x, zero
+// elsewhere (the zero boundary of Eq. 1).
+template <int M, bool ROWS>
+__global__ void __launch_bounds__(512) k_extrap_fast(ExtrapArgs a)
+{
+    extern __shared__ float4 smem4[];
+    float2* sm = reinterpret_cast<float2*>(smem4);
+    Lane L;
+    L.t = threadIdx.x;
+    L.r = blockIdx.x;
+    L.LB = 2 * blockDim.x + 2 * M + 2;
+    L.x0 = 2 * L.t;
+    L.ok0 = L.x0 < a.nx;
+    L.ok1 = L.x0 + 1 < a.nx;
+    L.ar = a.omega[L.r] / a.dk;
+
+    for (int i = L.t; i < 2 * L.LB; i += blockDim.x) sm[i] = make_float2(0.0f, 0.0f);
+    __syncthreads();
+    if (L.ok0) sm[M + L.x0] = a.win[(size_t)L.x0 * a.nw + L.r];
+    if (L.ok1) sm[M + L.x0 + 1] = a.win[(size_t)(L.x0 + 1) * a.nw + L.r];
+
+    float2 hA[2][M + 1], hB[2][M + 1];
+    unsigned long long bA[2], bB[2];
+    {
+        const double2 s0 = *reinterpret_cast<const double2*>(a.slow + L.x0);
+        bA[0] = dbits(s0.x);
+        bA[1] = dbits(s0.y);
+        load_taps<M>(hA[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s0.x) * (M + 1));
+        load_taps<M>(hA[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s0.y) * (M + 1));
+        const int k1 = a.nsteps > 1 ? 1 : 0;
+        const double2 s1 = *reinterpret_cast<const double2*>(a.slow + (size_t)k1 * a.ldp + L.x0);
+        bB[0] = dbits(s1.x);
+        bB[1] = dbits(s1.y);
+        load_taps<M>(hB[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s1.x) * (M + 1));
+        load_taps<M>(hB[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s1.y) * (M + 1));
+    }
+    double2 sn = make_double2(0.0, 0.0);
+    wait_vmem<0>();
+    __syncthreads();
+
+    float2 o0 = make_float2(0.0f, 0.0f), o1 = o0;
+    for (int k = 0; k < a.nsteps; k += 2) {
+        step_fast<M, ROWS>(a, sm, L, k, hA, hB, bB, sn, o0, o1);
+        if (k + 1 >= a.nsteps) break;
+        step_fast<M, ROWS>(a, sm, L, k + 1, hB, hA, bA, sn, o0, o1);
+    }
+    if (a.wout) {
+        if (L.ok0) a.wout[(size_t)L.x0 * a.nw + L.r] = o0;
+        if (L.ok1) a.wout[(size_t)(L.x0 + 1) * a.nw + L.r] = o1;
+    }
+}
+
 // Register-tap kernel for wider sections (nx <= 4 * 512): four outputs per
-// thread and one tap set, refilled at the end of a step for outputs whose
-// velocity changes at the next step.  A workgroup touches only the table rows
-// of its own frequency, so refills mostly hit in L1 and the barrier covers
-// their latency.
-template <int M>
+// thread and one tap set (two do not fit in 256 VGPRs), refilled at the end of
+// a step for outputs whose slowness changes at the next step.  A workgroup
+// touches only the table rows of its own frequency, so refills mostly hit in
+// L1 and the barrier covers part of their latency.
+template <int M, bool ROWS>
 __global__ void __launch_bounds__(512) k_extrap_wide(ExtrapArgs a)
 {
     extern __shared__ float4 smem4[];
@@ -218,12 +238,8 @@ __global__ void __launch_bounds__(512) k_extrap_wide(ExtrapArgs a)
     const int LB = 4 * blockDim.x + 2 * M + 4;
     const int x0 = 4 * t;
     bool ok[4];
-    int xc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ok[q] = x0 + q < a.nx;
-        xc[q] = ok[q] ? x0 + q : a.nx - 1;
-    }
+    for (int q = 0; q < 4; ++q) ok[q] = x0 + q < a.nx;
     const double ar = a.omega[r] / a.dk;
 
     for (int i = t; i < 2 * LB; i += blockDim.x) sm[i] = make_float2(0.0f, 0.0f);
@@ -233,51 +249,52 @@ __global__ void __launch_bounds__(512) k_extrap_wide(ExtrapArgs a)
         if (ok[q]) sm[M + x0 + q] = a.win[(size_t)(x0 + q) * a.nw + r];
 
     float2 h[4][M + 1];
-    unsigned bits[4];
-    float vn[4];
+    unsigned long long bits[4];
+    double sn[4];
+    {
+        const double2* s0 = reinterpret_cast<const double2*>(a.slow + x0);
+        const int k1 = a.nsteps > 1 ? 1 : 0;
+        const double2* s1 = reinterpret_cast<const double2*>(a.slow + (size_t)k1 * a.ldp + x0);
+        double c[4] = {s0[0].x, s0[0].y, s0[1].x, s0[1].y};
+        double n1[4] = {s1[0].x, s1[0].y, s1[1].x, s1[1].y};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float v = a.vel[xc[q]];
-        bits[q] = __float_as_uint(v);
-        load_taps<M>(h[q], a.tab + (size_t)table_index(ar, a.b, a.nk, v) * (M + 1));
-        vn[q] = a.nsteps > 1 ? a.vel[a.nx + xc[q]] : 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            bits[q] = dbits(c[q]);
+            load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, c[q]) * (M + 1));
+            sn[q] = n1[q];
+        }
     }
+    wait_vmem<0>();
     __syncthreads();
 
     float2 o[4];
     for (int k = 0; k < a.nsteps; ++k) {
-        float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (k + 2 < a.nsteps) {
-            const float* vr = a.vel + (size_t)(k + 2) * a.nx;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) p[q] = vr[xc[q]];
-        }
+        const int kp = k + 2 < a.nsteps ? k + 2 : a.nsteps - 1;
+        const double2* sp = reinterpret_cast<const double2*>(a.slow + (size_t)kp * a.ldp + x0);
+        const double2 p01 = sp[0], p23 = sp[1];
         fir4<M>(sm + (k & 1) * LB + x0, h, o);
         float2* dst = sm + ((k + 1) & 1) * LB + M + x0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (ok[q]) dst[q] = o[q];
-        if (a.part) {
+        if (ROWS) {
             float* pr = a.part + ((size_t)k * a.nw + r) * a.ldp + x0;
-            if (ok[3]) {
-                *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    if (ok[q]) pr[q] = o[q].x;
-            }
+            *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
         }
         if (k + 1 < a.nsteps) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                unsigned u = __float_as_uint(vn[q]);
+                unsigned long long u = dbits(sn[q]);
                 if (u != bits[q]) {
                     bits[q] = u;
-                    load_taps<M>(h[q], a.tab + (size_t)table_index(ar, a.b, a.nk, vn[q]) * (M + 1));
+                    load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, sn[q]) * (M + 1));
                 }
-                vn[q] = p[q];
             }
         }
+        sn[0] = p01.x;
+        sn[1] = p01.y;
+        sn[2] = p23.x;
+        sn[3] = p23.y;
         __syncthreads();
     }
     if (a.wout) {
@@ -303,9 +320,9 @@ __global__ void __launch_bounds__(256) k_extrap_general(ExtrapArgs a)
     for (int k = 0; k < a.nsteps; ++k) {
         const float2* src = sm + (k & 1) * LB + M;
         float2* dst = sm + ((k + 1) & 1) * LB + M;
-        const float* vr = a.vel + (size_t)k * nx;
+        const double* sr = a.slow + (size_t)k * a.ldp;
         for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const float2* h = a.tab + (size_t)table_index(ar, a.b, a.nk, vr[x]) * (M + 1);
+            const float2* h = a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, sr[x]) * (M + 1);
             float2 acc = cmulf(h[0], src[x]);
             for (int n = 1; n <= M; ++n) acc = cfmaf(h[n], cadd(src[x - n], src[x + n]), acc);
             dst[x] = acc;
@@ -370,7 +387,10 @@ int launch_fast(const ExtrapArgs& a, hipStream_t s)
 {
     int threads = ((a.nx + 1) / 2 + 63) / 64 * 64;
     size_t lds = (size_t)2 * (2 * threads + 2 * M + 2) * sizeof(float2);
-    hipLaunchKernelGGL(k_extrap_fast<M>, dim3(a.nw), dim3(threads), lds, s, a);
+    if (a.part)
+        hipLaunchKernelGGL((k_extrap_fast<M, true>), dim3(a.nw), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_extrap_fast<M, false>), dim3(a.nw), dim3(threads), lds, s, a);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
@@ -379,14 +399,17 @@ int launch_wide(const ExtrapArgs& a, hipStream_t s)
 {
     int threads = ((a.nx + 3) / 4 + 63) / 64 * 64;
     size_t lds = (size_t)2 * (4 * threads + 2 * M + 4) * sizeof(float2);
-    hipLaunchKernelGGL(k_extrap_wide<M>, dim3(a.nw), dim3(threads), lds, s, a);
+    if (a.part)
+        hipLaunchKernelGGL((k_extrap_wide<M, true>), dim3(a.nw), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_extrap_wide<M, false>), dim3(a.nw), dim3(threads), lds, s, a);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
 typedef int (*launch_fn)(const ExtrapArgs&, hipStream_t);
 
 // Register-tap kernels are instantiated for N = 1..35 (M = 0..17); beyond
-// that the two tap sets no longer fit in 256 VGPRs without spilling.
+// that two tap sets no longer fit in 256 VGPRs without spilling.
 #define MIG_INST(f)                                                                   \
     {&f<0>, &f<1>, &f<2>, &f<3>, &f<4>, &f<5>, &f<6>, &f<7>, &f<8>, &f<9>, &f<10>,     \
      &f<11>, &f<12>, &f<13>, &f<14>, &f<15>, &f<16>, &f<17>}
@@ -404,6 +427,16 @@ int extrap_kernel_kind(int nx, int M)
     if (nx <= kFastMaxNx) return 1;
     if (nx <= kWideMaxNx) return 2;
     return 0;
+}
+
+int launch_slowness(const float* vel, int nx, int nrows, int ldp, double* slow, hipStream_t s)
+{
+    size_t total = (size_t)nrows * ldp;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_slowness, dim3((unsigned)blocks), dim3(256), 0, s, vel, nx, nrows, ldp,
+                       slow);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
 int launch_extrap(const ExtrapArgs& a, hipStream_t s)

@@ -185,7 +185,7 @@ def extrapolate(wf, vel, omega, tab32, desc, nsteps=None, rows=True, out=None, w
     if out is not None:
         _need(out, torch.complex64, (nx, nw), "out")
     rws = torch.empty((nsteps, nx), dtype=torch.float64, device=wf.device) if rows else None
-    if rows and ws is None:
+    if ws is None and nsteps > 0:
         ws = torch.empty(max(workspace_size(nx, nsteps, nw, desc), 1), dtype=torch.uint8,
                          device=wf.device)
     cd = cdesc(desc)

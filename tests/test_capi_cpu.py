@@ -80,8 +80,11 @@ def test_workspace_sizes_and_kernel_kinds(L):
     full = mig.workspace_size(1024, 511, 200, d)
     one = mig.workspace_min_size(1024, 200, d)
     plane = 1024 * 200 * 8
-    assert one == plane + 200 * 1024 * 4
-    assert full == plane + 511 * 200 * 1024 * 4
+    step = 1024 * 8 + 200 * 1024 * 4          # slowness row + partial rows
+    assert one == plane + step
+    assert full == plane + 511 * step
+    plane_1000 = (1000 * 7 * 8 + 255) // 256 * 256
+    assert mig.workspace_size(1000, 3, 7, d) == plane_1000 + 3 * (1024 * 8 + 7 * 1024 * 4)
     assert mig.kernel_kind(1024, 35) == 1
     assert mig.kernel_kind(1025, 35) == 2
     assert mig.kernel_kind(2048, 25) == 2

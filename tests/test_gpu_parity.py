@@ -2,8 +2,12 @@
 
 Tolerances
   * table design (FP64 on both sides, same formulas, same accumulation order;
-    only libm vs device cos/sin/exp/hypot differ in the last bit): 1e-10
-    relative to the largest tap;
+    only libm vs device cos/sin/exp/hypot differ in the last bit).  The
+    reweighting passes multiply weights by 1 + (|H|-1)/tau with tau = 1e-4, a
+    gain of 1e4, so the design map itself is ill-conditioned: a 1-ulp change
+    of dx, dz or tau moves the oracle's own table by up to ~1e-8 (config 2).
+    The bound is therefore 4x the oracle's measured 1-ulp sensitivity (plus
+    1e-12), which stays below the FP32 rounding of the taps (6e-8);
   * table look-up: bit-exact (same IEEE-double operation sequence);
   * FP32 extrapolation vs FP64 oracle: relative L2 <= 1e-5 after a few steps
     (FP32 taps and arithmetic, ~1e-7 per operation, ~2N operations per output
@@ -11,6 +15,8 @@ Tolerances
   * imaging of the same complex64 plane: FP64 sums in a different order,
     1e-13 relative.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -33,16 +39,30 @@ def tables():
     return get
 
 
+def _ulp_sensitivity(desc, ot):
+    """Largest relative change of the oracle's table under 1-ulp changes of
+    (dx, dz) and of tau."""
+    worst = 0.0
+    for kw in ({"dx": np.nextafter(desc.dx, np.inf), "dz": np.nextafter(desc.dz, np.inf)},
+               {"tau": np.nextafter(desc.tau, np.inf)}):
+        t1 = oracle.design_table(dataclasses.replace(desc, **kw))[0]
+        worst = max(worst, float(np.abs(t1 - ot).max() / np.abs(ot).max()))
+    return worst
+
+
 @pytest.mark.parametrize("which", ["cfg1", "cfg2"])
 def test_design_table_matches_oracle(which, tables, cfg1, cfg2_model):
     desc = (cfg1 if which == "cfg1" else cfg2_model).desc
     (ot, omg, ope, _), g = tables(desc)
     t64 = g["tab64"].cpu().numpy()
     err = np.abs(t64 - ot).max() / np.abs(ot).max()
-    print("%s table max rel diff %.3e" % (which, err))
-    assert err <= 1e-10
-    assert np.abs(g["maxgain"].cpu().numpy() - omg).max() <= 1e-10
-    assert np.abs(g["passerr"].cpu().numpy() - ope).max() <= 1e-10
+    sens = _ulp_sensitivity(desc, ot)
+    tol = 4.0 * sens + 1e-12
+    print("%s table max rel diff %.3e; oracle 1-ulp sensitivity %.3e" % (which, err, sens))
+    assert tol < 6e-8
+    assert err <= tol
+    assert np.abs(g["maxgain"].cpu().numpy() - omg).max() <= tol
+    assert np.abs(g["passerr"].cpu().numpy() - ope).max() <= tol
     assert float(g["maxgain"].max()) <= 1.0
     assert torch.equal(g["tab32"], g["tab64"].to(torch.complex64))
 
