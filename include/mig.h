@@ -204,6 +204,47 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel,
                         int32_t nw, double* image, void* ws, size_t ws_bytes,
                         void* stream);
 
+/*
+ * Batched form: many independent 2-D sections (different nx, nz, nw, all
+ * sharing one table) migrated in at most three launches -- one per kernel
+ * variant -- instead of one per section.  Every section is Algorithm 1 end to
+ * end exactly as mig_migrate computes it (bit-identical results for the same
+ * tuning), so this is a scheduling form of the same method: frequency
+ * workgroups of all sections are interleaved longest-first, and the image
+ * reduction over frequencies of all sections runs in the same launches.
+ *   secs   [nsec] host array of section descriptors (read during the call)
+ *   tune   knobs chosen by an autotuner, or NULL for the library defaults
+ *   ws     >= mig_batch_workspace_size(secs, nsec, d, tune) bytes of device
+ *          memory (slowness rows, partial image rows and descriptors of every
+ *          section; no chunking)
+ */
+typedef struct {
+    const mig_c64* data;   /* [nx][nw] surface plane                        */
+    const float* vel;      /* [nz][nx] propagation velocity                  */
+    const double* omega;   /* [nw]                                           */
+    double* image;         /* [nz][nx] output; row 0 = image of data         */
+    int32_t nx, nz, nw;    /* nx <= MIG_MAX_NX, nz >= 1, nw >= 1             */
+    int32_t reserved;      /* must be 0                                      */
+} mig_section;
+
+typedef struct {
+    int32_t omegas_per_group; /* frequencies per workgroup in the two-output
+                                 register-tap kernel (0 = as many as fit in
+                                 512 threads); clamped to what fits          */
+    int32_t reducers;         /* reducer workgroups per launch, 8..64
+                                 (0 = the CUs the frequency workgroups leave
+                                 idle, at least 8)                           */
+    int32_t reserved[2];      /* must be 0                                   */
+} mig_tuning;
+
+MIG_API size_t mig_batch_workspace_size(const mig_section* secs, int32_t nsec,
+                                        const mig_table_desc* d,
+                                        const mig_tuning* tune);
+MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec,
+                                const mig_c64* tab32, const mig_table_desc* d,
+                                const mig_tuning* tune, void* ws,
+                                size_t ws_bytes, void* stream);
+
 /* Diagnostic query: which extrapolation kernel a call with these sizes takes.
  * 1 = register-tap kernel, two outputs per thread (N <= 35, nx <= 1024);
  * 2 = register-tap kernel, four outputs per thread (N <= 35, nx <= 2048);

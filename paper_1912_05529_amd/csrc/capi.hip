@@ -4,6 +4,9 @@
 // launches kernels; every arithmetic step of the method runs on the GPU.
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 
 using namespace mig;
@@ -55,34 +58,90 @@ size_t step_bytes(int nx, int nw, bool rows)
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
-// Depth loop, split into chunks that fit the workspace.  Workspace layout:
-// [scratch plane][slowness chunk x ldp doubles][partials chunk x nw x ldp floats].
+// Fixed workspace region for the published-block counters of one launch.
+constexpr size_t kCounterBytes = 16384;
+constexpr int kMaxBlocks = (int)(kCounterBytes / sizeof(int));
+constexpr int kMaxChunk = kMaxBlocks * kPublish;
+constexpr int kMaxThreads = 512;
+
+int device_cus()
+{
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 256;
+    return ncu;
+}
+
+// Reducer workgroups beside `nprod` frequency workgroups: the CUs they leave
+// idle, at least 8, at most 64 and the number of reduction tasks.
+int reducer_count(int nprod, int ntasks, int want)
+{
+    int n = want > 0 ? want : device_cus() - nprod;
+    if (n < 8) n = 8;
+    if (n > 64) n = 64;
+    return n < ntasks ? n : ntasks;
+}
+
+// Frequencies per workgroup for one section in the register-tap kernel with two
+// outputs per thread: `want` if given (clamped to what fits), else 1.
+int omegas_per_group(int kind, int nx, int want)
+{
+    if (kind != 1) return 1;
+    int fit = kMaxThreads / threads_per_omega(1, nx);
+    if (fit < 1) fit = 1;
+    int g = want > 0 ? want : 1;
+    return g < fit ? g : fit;
+}
+
+struct Tuning {
+    int G;      // frequencies per workgroup (0 = default)
+    int nred;   // reducer workgroups (0 = default)
+};
+
+// Depth loop of one section, split into chunks that fit the workspace.
+// Workspace layout: [scratch plane][counters][trash row][slowness chunk x ldp
+// doubles][partials chunk x nw x ldp floats].
 int run_extrap(const float2* src, float2* dst, const float* vel, const double* omega,
                const float2* tab, const mig_table_desc* d, int nx, int nw, int nsteps,
-               double* rows, void* ws, size_t ws_bytes, hipStream_t s)
+               double* rows, void* ws, size_t ws_bytes, hipStream_t s, const Tuning& tn)
 {
-    const size_t pb = plane_bytes(nx, nw);
-    const size_t sb = step_bytes(nx, nw, rows != nullptr);
-    if (!ws || ws_bytes < pb + sb) return MIG_E_WORKSPACE;
-    size_t fit = (ws_bytes - pb) / sb;
-    const int chunk = fit >= (size_t)nsteps ? nsteps : (int)fit;
     const int ldp = row_stride(nx);
-    // ldp is a multiple of 256, so every region below starts 2 KB-aligned.
-    float2* scratch = static_cast<float2*>(ws);
-    double* slow = reinterpret_cast<double*>(static_cast<char*>(ws) + pb);
-    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + pb +
-                                           (size_t)chunk * ldp * sizeof(double));
+    const size_t head = plane_bytes(nx, nw) + kCounterBytes + (size_t)ldp * sizeof(float);
+    const size_t sb = step_bytes(nx, nw, rows != nullptr);
+    if (!ws || ws_bytes < head + sb) return MIG_E_WORKSPACE;
+    size_t fit = (ws_bytes - head) / sb;
+    int chunk = fit >= (size_t)nsteps ? nsteps : (int)fit;
+    if (chunk > kMaxChunk) chunk = kMaxChunk;
+    // ldp is a multiple of 256, so every region below stays 1 KB-aligned.
+    char* base = static_cast<char*>(ws);
+    float2* scratch = reinterpret_cast<float2*>(base);
+    int* cnt = reinterpret_cast<int*>(base + plane_bytes(nx, nw));
+    float* trash = reinterpret_cast<float*>(base + plane_bytes(nx, nw) + kCounterBytes);
+    double* slow = reinterpret_cast<double*>(base + head);
+    float* part = reinterpret_cast<float*>(base + head + (size_t)chunk * ldp * sizeof(double));
 
-    ExtrapArgs a;
-    a.omega = omega;
+    const int M = (d->ntaps - 1) / 2;
+    const int kind = extrap_kernel_kind(nx, M);
+    const int G = omegas_per_group(kind, nx, tn.G);
+    const int nitems = (nw + G - 1) / G;
+
+    BatchArgs a = {};
+    a.one.omega = omega;
+    a.one.slow = slow;
+    a.one.part = rows ? part : nullptr;
+    a.one.cnt = cnt;
+    a.one.nx = nx;
+    a.one.nw = nw;
+    a.one.ldp = ldp;
+    a.one.nprod = nitems;
+    a.one.G = G;
     a.tab = tab;
-    a.slow = slow;
-    a.part = rows ? part : nullptr;
-    a.nx = nx;
-    a.nw = nw;
+    a.trash = trash;
+    a.nsec = 1;
+    a.nitems = nitems;
     a.nk = d->nk;
-    a.M = (d->ntaps - 1) / 2;
-    a.ldp = ldp;
+    a.M = M;
     a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
     a.b = d->kmin / a.dk;
 
@@ -90,25 +149,193 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
     for (int c0 = 0; c0 < nsteps; c0 += chunk) {
         int cs = nsteps - c0 < chunk ? nsteps - c0 : chunk;
         bool last = c0 + cs == nsteps;
-        int rc = launch_slowness(vel + (size_t)c0 * nx, nx, cs, ldp, slow, s);
-        if (rc != MIG_OK) return rc;
-        a.win = cur;
+        a.one.win = cur;
         // Intermediate planes go to the scratch plane, in place: each workgroup
-        // reads its whole frequency column before writing it back.
-        a.wout = last ? dst : scratch;
-        a.nsteps = cs;
-        rc = launch_extrap(a, s);
-        if (rc != MIG_OK) return rc;
-        if (rows) {
-            rc = launch_rows_reduce(part, ldp, nx, nw, cs, rows + (size_t)c0 * nx, s);
-            if (rc != MIG_OK) return rc;
+        // reads its whole frequency columns before writing them back.
+        a.one.wout = last ? dst : scratch;
+        a.one.vel = vel + (size_t)c0 * nx;
+        a.one.nsteps = cs;
+        a.one.rows = rows ? rows + (size_t)c0 * nx : nullptr;
+        a.ntasks = rows ? cs : 0;
+        a.nred = rows ? reducer_count(nitems, cs, tn.nred) : 0;
+        int rc = launch_slowness(a, cs, ldp, flag_distance(kind), s);
+        if (rc == MIG_OK && rows) rc = launch_zero(cnt, (cs + kPublish - 1) / kPublish, s);
+        if (rc == MIG_OK) {
+            if (kind == 0) rc = launch_general(a, nx, s);
+            else rc = launch_extrap(a, kind, G * threads_per_omega(kind, nx), s);
         }
+        if (rc != MIG_OK) return rc;
         cur = scratch;
     }
     return MIG_OK;
 }
 
 bool sizes_ok(int nx, int nw) { return nx >= 1 && nx <= MIG_MAX_NX && nw >= 1 && nw <= MIG_MAX_NW; }
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent sections in at most three launches (one per
+// kernel variant).  The layout of the workspace is computed by one planner,
+// used both by the size query (base == nullptr) and by the run.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    size_t bytes = 0;
+    struct Group {
+        int kind = 0, threads = 0, max_nx = 0, max_rows = 0, max_ldp = 0;
+        std::vector<SecDev> secs;
+        std::vector<ItemDev> items;
+        std::vector<TaskDev> tasks;
+        size_t desc_off = 0, desc_bytes = 0;  // SecDev + ItemDev + TaskDev arrays
+        size_t cnt_off = 0;
+        int ncnt = 0;
+    } group[3];
+    size_t trash_off = 0;
+};
+
+size_t bump(size_t& off, size_t n)
+{
+    size_t at = align_up(off, kAlign);
+    off = at + n;
+    return at;
+}
+
+bool sections_ok(const mig_section* secs, int nsec)
+{
+    if (!secs || nsec < 1) return false;
+    for (int i = 0; i < nsec; ++i) {
+        const mig_section& q = secs[i];
+        if (!q.data || !q.vel || !q.omega || !q.image || !sizes_ok(q.nx, q.nw) || q.nz < 1 ||
+            q.reserved != 0)
+            return false;
+    }
+    return true;
+}
+
+void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, const Tuning& tn,
+                char* base, BatchPlan& P)
+{
+    const int M = (d->ntaps - 1) / 2;
+    size_t off = 0;
+    int max_ldp = 0;
+    for (int i = 0; i < nsec; ++i) max_ldp = row_stride(secs[i].nx) > max_ldp ? row_stride(secs[i].nx) : max_ldp;
+    P.trash_off = bump(off, (size_t)max_ldp * sizeof(float));
+    for (int i = 0; i < nsec; ++i) {
+        const mig_section& q = secs[i];
+        if (q.nz < 2) continue;
+        const int kind = extrap_kernel_kind(q.nx, M);
+        BatchPlan::Group& g = P.group[kind];
+        g.kind = kind;
+        SecDev S = {};
+        S.win = reinterpret_cast<const float2*>(q.data);
+        S.wout = nullptr;
+        S.vel = q.vel;
+        S.omega = q.omega;
+        S.rows = q.image + q.nx;
+        S.nx = q.nx;
+        S.nw = q.nw;
+        S.nsteps = q.nz - 1;
+        S.ldp = row_stride(q.nx);
+        S.G = omegas_per_group(kind, q.nx, tn.G > 0 ? tn.G : kMaxThreads);
+        S.nprod = (q.nw + S.G - 1) / S.G;
+        size_t so = bump(off, (size_t)S.nsteps * S.ldp * sizeof(double));
+        size_t po = bump(off, (size_t)S.nsteps * S.nw * S.ldp * sizeof(float));
+        S.slow = reinterpret_cast<const double*>(base ? base + so : nullptr);
+        S.part = reinterpret_cast<float*>(base ? base + po : nullptr);
+        S.cnt = reinterpret_cast<int*>((size_t)g.ncnt);  // offset, fixed up below
+        g.ncnt += (S.nsteps + kPublish - 1) / kPublish;
+        const int tpo = threads_per_omega(kind, q.nx);
+        const int th = kind == 0 ? 256 : S.G * tpo;
+        g.threads = th > g.threads ? th : g.threads;
+        g.max_nx = q.nx > g.max_nx ? q.nx : g.max_nx;
+        g.max_rows = S.nsteps > g.max_rows ? S.nsteps : g.max_rows;
+        g.max_ldp = S.ldp > g.max_ldp ? S.ldp : g.max_ldp;
+        g.secs.push_back(S);
+    }
+    for (int k = 0; k < 3; ++k) {
+        BatchPlan::Group& g = P.group[k];
+        if (g.secs.empty()) continue;
+        g.cnt_off = bump(off, (size_t)g.ncnt * sizeof(int));
+        for (SecDev& S : g.secs)
+            S.cnt = reinterpret_cast<int*>(base ? base + g.cnt_off + (size_t)S.cnt * sizeof(int) : nullptr);
+        // Items: longest first (depth steps x points), so the tail of the
+        // launch is made of short items.
+        std::vector<int> order(g.secs.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return (long long)g.secs[x].nsteps * g.secs[x].nx > (long long)g.secs[y].nsteps * g.secs[y].nx;
+        });
+        for (int si : order)
+            for (int r0 = 0; r0 < g.secs[si].nw; r0 += g.secs[si].G) g.items.push_back(ItemDev{si, r0});
+        // Reducer tasks step-major across sections (production order).
+        for (int st = 0; st < g.max_rows; ++st)
+            for (int si : order)
+                if (st < g.secs[si].nsteps) g.tasks.push_back(TaskDev{si, st});
+        g.desc_bytes = g.secs.size() * sizeof(SecDev) + g.items.size() * sizeof(ItemDev) +
+                       g.tasks.size() * sizeof(TaskDev);
+        g.desc_off = bump(off, g.desc_bytes);
+    }
+    P.bytes = align_up(off, kAlign);
+}
+
+int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_table_desc* d,
+              const Tuning& tn, void* ws, size_t ws_bytes, hipStream_t s)
+{
+    BatchPlan P;
+    char* base = static_cast<char*>(ws);
+    plan_batch(secs, nsec, d, tn, base, P);
+    if (!ws || ws_bytes < P.bytes) return MIG_E_WORKSPACE;
+    for (int i = 0; i < nsec; ++i) {
+        int rc = launch_image(reinterpret_cast<const float2*>(secs[i].data), secs[i].image,
+                              secs[i].nx, secs[i].nw, s);
+        if (rc != MIG_OK) return rc;
+    }
+    const int M = (d->ntaps - 1) / 2;
+    // wide sections first: their items are the longest
+    const int kinds[3] = {2, 1, 0};
+    for (int kk = 0; kk < 3; ++kk) {
+        BatchPlan::Group& g = P.group[kinds[kk]];
+        if (g.secs.empty()) continue;
+        std::vector<char> host(g.desc_bytes);
+        size_t o = 0;
+        memcpy(host.data() + o, g.secs.data(), g.secs.size() * sizeof(SecDev));
+        o += g.secs.size() * sizeof(SecDev);
+        memcpy(host.data() + o, g.items.data(), g.items.size() * sizeof(ItemDev));
+        o += g.items.size() * sizeof(ItemDev);
+        memcpy(host.data() + o, g.tasks.data(), g.tasks.size() * sizeof(TaskDev));
+        char* dev = base + g.desc_off;
+        if (hipMemcpyAsync(dev, host.data(), g.desc_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return MIG_E_DEVICE;
+        BatchArgs a = {};
+        a.secs = reinterpret_cast<const SecDev*>(dev);
+        a.items = reinterpret_cast<const ItemDev*>(dev + g.secs.size() * sizeof(SecDev));
+        a.tasks = reinterpret_cast<const TaskDev*>(dev + g.secs.size() * sizeof(SecDev) +
+                                                   g.items.size() * sizeof(ItemDev));
+        a.tab = tab;
+        a.trash = reinterpret_cast<float*>(base + P.trash_off);
+        a.nsec = (int)g.secs.size();
+        a.nitems = (int)g.items.size();
+        a.ntasks = (int)g.tasks.size();
+        a.nred = reducer_count(a.nitems, a.ntasks, tn.nred);
+        a.nk = d->nk;
+        a.M = M;
+        a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
+        a.b = d->kmin / a.dk;
+        if (a.nsec == 1) {
+            // a batch of one section uses the argument-resident descriptor
+            a.one = g.secs[0];
+            a.secs = nullptr;
+            a.items = nullptr;
+            a.tasks = nullptr;
+        }
+        int rc = launch_zero(reinterpret_cast<int*>(base + g.cnt_off), g.ncnt, s);
+        if (rc == MIG_OK) rc = launch_slowness(a, g.max_rows, g.max_ldp, flag_distance(g.kind), s);
+        if (rc == MIG_OK) {
+            if (g.kind == 0) rc = launch_general(a, g.max_nx, s);
+            else rc = launch_extrap(a, g.kind, g.threads, s);
+        }
+        if (rc != MIG_OK) return rc;
+    }
+    return MIG_OK;
+}
 
 }  // namespace
 
@@ -187,13 +414,15 @@ MIG_API size_t mig_workspace_size(int32_t nx, int32_t nsteps, int32_t nw, const 
 {
     if (!desc_valid(d) || !sizes_ok(nx, nw) || nsteps < 0) return 0;
     size_t steps = nsteps > 0 ? (size_t)nsteps : 1;
-    return plane_bytes(nx, nw) + steps * step_bytes(nx, nw, true);
+    return plane_bytes(nx, nw) + kCounterBytes + (size_t)row_stride(nx) * sizeof(float) +
+           steps * step_bytes(nx, nw, true);
 }
 
 MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw, const mig_table_desc* d)
 {
     if (!desc_valid(d) || !sizes_ok(nx, nw)) return 0;
-    return plane_bytes(nx, nw) + step_bytes(nx, nw, true);
+    return plane_bytes(nx, nw) + kCounterBytes + (size_t)row_stride(nx) * sizeof(float) +
+           step_bytes(nx, nw, true);
 }
 
 MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out, const float* vel,
@@ -217,7 +446,7 @@ MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out, const float* 
     if (ws && (overlap(ws, ws_bytes, wf_in, pl) || (wf_out && overlap(ws, ws_bytes, wf_out, pl))))
         return MIG_E_ARG;
     return run_extrap(src, dst, vel, omega, reinterpret_cast<const float2*>(tab32), d, nx, nw,
-                      nsteps, rows, ws, ws_bytes, s);
+                      nsteps, rows, ws, ws_bytes, s, Tuning{0, 0});
 }
 
 MIG_API int mig_image(const mig_c64* wf, double* row, int32_t nx, int32_t nw, void* stream)
@@ -240,7 +469,34 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel, const double* ome
     if (ws && overlap(ws, ws_bytes, data, pl)) return MIG_E_ARG;
     return run_extrap(reinterpret_cast<const float2*>(data), nullptr, vel, omega,
                       reinterpret_cast<const float2*>(tab32), d, nx, nw, nz - 1, image + nx, ws,
-                      ws_bytes, s);
+                      ws_bytes, s, Tuning{0, 0});
+}
+
+MIG_API size_t mig_batch_workspace_size(const mig_section* secs, int32_t nsec,
+                                        const mig_table_desc* d, const mig_tuning* tune)
+{
+    if (!desc_valid(d) || !sections_ok(secs, nsec)) return 0;
+    Tuning tn{tune ? tune->omegas_per_group : 0, tune ? tune->reducers : 0};
+    BatchPlan P;
+    plan_batch(secs, nsec, d, tn, nullptr, P);
+    return P.bytes;
+}
+
+MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec, const mig_c64* tab32,
+                                const mig_table_desc* d, const mig_tuning* tune, void* ws,
+                                size_t ws_bytes, void* stream)
+{
+    if (!desc_valid(d) || !tab32 || !sections_ok(secs, nsec)) return MIG_E_ARG;
+    if (tune && (tune->omegas_per_group < 0 || tune->reducers < 0 || tune->reserved[0] != 0 ||
+                 tune->reserved[1] != 0))
+        return MIG_E_ARG;
+    for (int i = 0; i < nsec; ++i) {
+        const size_t pl = (size_t)secs[i].nx * secs[i].nw * sizeof(mig_c64);
+        if (ws && overlap(ws, ws_bytes, secs[i].data, pl)) return MIG_E_ARG;
+    }
+    Tuning tn{tune ? tune->omegas_per_group : 0, tune ? tune->reducers : 0};
+    return run_batch(secs, nsec, reinterpret_cast<const float2*>(tab32), d, tn, ws, ws_bytes,
+                     as_stream(stream));
 }
 
 // Internal query used by tests and the benchmark: which extrapolation kernel

@@ -11,15 +11,49 @@ namespace mig {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Arguments of the depth-stepping kernels (one workgroup per frequency).
-struct ExtrapArgs {
+// Frequency workgroups publish their partial rows every kPublish depth steps.
+constexpr int kPublish = 16;
+// Reducers give up (and write NaN rows) after this long without progress.
+constexpr unsigned long long kStallTicks = 20ull * 100000000ull;  // 20 s at 100 MHz
+
+// One section as the depth-stepping kernels see it (device pointers).
+struct SecDev {
     const float2* win;     // [nx][nw] plane at the first depth of the launch
     float2* wout;          // [nx][nw] plane after nsteps, or nullptr
+    const float* vel;      // [nsteps][nx] propagation velocity rows
     const double* slow;    // [nsteps][ldp] slowness rows (see slowness_of)
     const double* omega;   // [nw]
-    const float2* tab;     // [nk][M+1] complex64 half-taps
     float* part;           // [nsteps][nw][ldp] Re of each new plane, or nullptr
-    int nx, nw, nsteps, nk, M, ldp;
+    double* rows;          // [nsteps][nx] image rows, or nullptr
+    int* cnt;              // [ceil(nsteps/kPublish)] published-block counters
+    int nx, nw, nsteps, ldp;
+    int nprod;             // frequency workgroups of this section in the launch
+    int G;                 // frequencies per workgroup (sub-groups of tsub threads)
+};
+
+// A frequency workgroup: section and first frequency (it owns G of them).
+struct ItemDev {
+    int sec, r0;
+};
+
+// A reducer task: image row `step` of section `sec`.
+struct TaskDev {
+    int sec, step;
+};
+
+// Arguments of one depth-stepping launch.  With nsec == 1 the section lives
+// in `one`, workgroup i owns frequencies [i*G, i*G+G) (G = one.G) and reducer
+// task i is step i; otherwise the three arrays (device memory) describe the
+// batch.
+struct BatchArgs {
+    SecDev one;
+    const SecDev* secs;
+    const ItemDev* items;
+    const TaskDev* tasks;
+    const float2* tab;     // [nk][M+1] complex64 half-taps
+    float* trash;          // [ldp_max] sink for partial rows of idle sub-groups
+    int nsec, nitems, ntasks, nred;
+    int nk, M;
     double dk;             // table spacing (kmax-kmin)/(nk-1)
     double b;              // kmin / dk
 };
@@ -29,6 +63,22 @@ struct ExtrapArgs {
 __device__ __forceinline__ double slowness_of(float v)
 {
     return v > 0.0f ? 1.0 / (double)v : __builtin_nan("");
+}
+
+// The slowness rows handed to the depth-stepping kernels carry one flag in the
+// sign bit (slowness itself is never negative): set when the value differs
+// from the one `dist` rows earlier, i.e. when a tap set last loaded for that
+// row must be refilled.
+constexpr unsigned long long kSignBit = 0x8000000000000000ull;
+
+__device__ __forceinline__ bool slowness_changed(double s)
+{
+    return (__double_as_longlong(s) & (long long)kSignBit) != 0;
+}
+
+__device__ __forceinline__ double slowness_value(double s)
+{
+    return __longlong_as_double(__double_as_longlong(s) & (long long)~kSignBit);
 }
 
 // Table look-up of Algorithm 1: nearest entry to omega/v, as the IEEE-double
@@ -55,6 +105,14 @@ __device__ __forceinline__ int table_index(double a, double b, int nk, float v)
 // every thread of the register-tap kernels can load and store whole vectors.
 inline int row_stride(int nx) { return (nx + 255) / 256 * 256; }
 
+// Kernel variants (tests and the benchmark can query which one runs):
+// 1 = register taps, two outputs per thread, two tap sets (nx <= 1024);
+// 2 = register taps, four outputs per thread, one tap set (nx <= 2048);
+// 0 = general kernel, taps read from the table every step.
+int extrap_kernel_kind(int nx, int M);
+// Threads one frequency needs in kernel `kind` for nx points.
+int threads_per_omega(int kind, int nx);
+
 // Host launchers (return MIG_OK or MIG_E_DEVICE).
 int launch_design_basis(const mig_table_desc* d, double* A, double* C, hipStream_t s);
 int launch_design(const mig_table_desc* d, const double* A, const double* C,
@@ -63,17 +121,17 @@ int launch_design(const mig_table_desc* d, const double* A, const double* C,
 int launch_index(const float* vel, const double* omega, int nx, int nw,
                  int nrows, int nk, double dk, double b, int32_t* idx,
                  hipStream_t s);
-int launch_slowness(const float* vel, int nx, int nrows, int ldp, double* slow, hipStream_t s);
-int launch_extrap(const ExtrapArgs& a, hipStream_t s);
-int launch_rows_reduce(const float* part, int ldp, int nx, int nw, int nsteps,
-                       double* rows, hipStream_t s);
+// Slowness rows of every section of the launch (one launch for all), with the
+// change flag taken against the row `dist` steps earlier (0 = no flags).
+int launch_slowness(const BatchArgs& a, int max_rows, int max_ldp, int dist, hipStream_t s);
+// Row distance of the change flag a kernel variant reads.
+inline int flag_distance(int kind) { return kind == 1 ? 2 : (kind == 2 ? 1 : 0); }
+// Depth stepping for every workgroup item (+ reducers when sections want rows).
+// `kind` and `threads` (workgroup size) are the same for all items.
+int launch_extrap(const BatchArgs& a, int kind, int threads, hipStream_t s);
+int launch_general(const BatchArgs& a, int max_nx, hipStream_t s);
+int launch_zero(int* p, int n, hipStream_t s);
 int launch_image(const float2* wf, double* row, int nx, int nw, hipStream_t s);
-
-// Which extrapolation kernel a launch with these sizes takes (for tests and
-// the benchmark): 1 = register-tap kernel (two outputs per thread, two tap
-// sets), 2 = register-tap kernel (four outputs per thread, one tap set),
-// 0 = general kernel.
-int extrap_kernel_kind(int nx, int M);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

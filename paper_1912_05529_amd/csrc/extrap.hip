@@ -3,38 +3,48 @@
 // Design (MI355X / gfx950):
 //   * Frequencies never interact during extrapolation (Sec. II: the process
 //     runs independently for each frequency), only through the image sum.  So
-//     one workgroup owns one frequency for the whole depth range: its plane
-//     (nx complex64, a few KB) stays in LDS, depth steps are separated by a
-//     workgroup barrier instead of a kernel exit (the "block level
-//     synchronization" the paper names as future work, Sec. V), and there is no
-//     inter-workgroup traffic at all.
+//     a frequency is owned by one workgroup for the whole depth range: its
+//     plane (nx complex64, a few KB) stays in LDS, depth steps are separated by
+//     a workgroup barrier instead of a kernel exit (the "block level
+//     synchronization" the paper names as future work, Sec. V), and there is
+//     no traffic between frequency workgroups.
+//   * A workgroup item owns G frequencies of one section (G sub-groups of
+//     `tsub` threads; G > 1 fills a workgroup when nx is small).  Items of many
+//     sections of different nx, nz and nw run in one launch (the batched form).
 //   * Lanes run along x (coalesced, conflict-free LDS windows); each thread
 //     owns two (or four) adjacent outputs and reads its window with 16-byte LDS
 //     loads.  Even taps are folded: h_n (u[x-n] + u[x+n]).
 //   * Taps live in registers.  The filter of an output only changes when the
-//     velocity under it changes (omega is fixed per workgroup), which in layered
-//     media is a few times per column.  Two register sets alternate between
-//     even and odd steps; the set for step k+1 is refilled during step k only
-//     for outputs whose slowness changed, so table reads (L2-resident) are rare
-//     and their latency is hidden behind a full step of arithmetic.
+//     velocity under it changes (omega is fixed per sub-group), which in
+//     layered media is a few times per column.  Two register sets alternate
+//     between even and odd steps; the set for step k+1 is refilled during step
+//     k only for outputs whose slowness changed, so table reads (L2-resident)
+//     are rare and their latency is hidden behind a full step of arithmetic.
+//     All vector-memory operations of a step are issued at its start (last
+//     step's partial row, refills, slowness prefetch), so one wait at the top
+//     of the next step finds them long complete.
 //   * The look-up needs 1/v in FP64; it is computed once per (depth, x) by a
 //     small pre-pass (shared by all frequencies) instead of once per refill.
 //   * The image row needs a sum over frequencies, i.e. across workgroups.
-//     Each workgroup writes Re of its new plane (float32, exact) to a partial
-//     buffer [step][omega][x]; a second kernel sums over omega in a fixed order
-//     in FP64, so images are run-to-run identical.
+//     Each frequency sub-group writes Re of its new plane (float32, exact) to a
+//     partial buffer [step][omega][x]; every kPublish steps the workgroup
+//     publishes its progress (agent-scope release + counter increment).
+//     Reducer workgroups in the same launch -- on CUs the frequency workgroups
+//     leave idle -- wait for a block of steps to be published by every
+//     workgroup of the section and sum it over omega in increasing order in
+//     FP64, so images are run-to-run identical and the reduction overlaps the
+//     extrapolation.  Frequency workgroups never wait on anyone; reducer waits
+//     are bounded (a stall of kStallTicks writes NaN rows instead of hanging).
 #include "common.hpp"
 
 namespace mig {
 namespace {
 
-// s_waitcnt vmcnt(N) with the other counters left alone (GFX9 encoding:
+// s_waitcnt vmcnt(0), other counters left alone (GFX9 encoding:
 // vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] in bits 15:14).
-template <int N>
-__device__ __forceinline__ void wait_vmem()
+__device__ __forceinline__ void wait_vmem_all()
 {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
 }
 
 __device__ __forceinline__ float2 cmulf(float2 h, float2 u)
@@ -54,11 +64,6 @@ __device__ __forceinline__ float2 cfmaf(float2 h, float2 s, float2 acc)
 __device__ __forceinline__ float2 cadd(float2 a, float2 b)
 {
     return make_float2(a.x + b.x, a.y + b.y);
-}
-
-__device__ __forceinline__ unsigned long long dbits(double d)
-{
-    return (unsigned long long)__double_as_longlong(d);
 }
 
 template <int M>
@@ -114,113 +119,239 @@ __device__ __forceinline__ void fir4(const float2* __restrict__ win, const float
     }
 }
 
-// slow[k][x] = slowness_of(vel[k][min(x, nx-1)]) for x < ldp.
-__global__ void k_slowness(const float* __restrict__ vel, int nx, int nrows, int ldp,
-                           double* __restrict__ slow)
+__device__ __forceinline__ SecDev sec_of(const BatchArgs& a, int i)
 {
-    const size_t total = (size_t)nrows * ldp;
+    return a.nsec == 1 ? a.one : a.secs[i];
+}
+
+__device__ __forceinline__ ItemDev item_of(const BatchArgs& a, int i)
+{
+    return a.nsec == 1 ? ItemDev{0, i * a.one.G} : a.items[i];
+}
+
+__device__ __forceinline__ TaskDev task_of(const BatchArgs& a, int i)
+{
+    return a.nsec == 1 ? TaskDev{0, i} : a.tasks[i];
+}
+
+// Per-workgroup constants: frequencies per workgroup and sub-group size.
+__device__ __forceinline__ void group_shape(const SecDev& S, int kind, int& G, int& tsub)
+{
+    tsub = kind == 1 ? ((S.nx + 1) / 2 + 63) / 64 * 64 : ((S.nx + 3) / 4 + 63) / 64 * 64;
+    G = S.G;
+}
+
+// slow[k][x] = slowness_of(vel[k][min(x, nx-1)]) for x < ldp, every section,
+// with the sign bit set where it differs (bitwise) from row k - dist.
+__global__ void k_slowness(BatchArgs a, int dist)
+{
+    const SecDev S = sec_of(a, blockIdx.y);
+    double* slow = const_cast<double*>(S.slow);
+    const size_t total = (size_t)S.nsteps * S.ldp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        size_t k = e / ldp;
-        int x = (int)(e % ldp);
-        slow[e] = slowness_of(vel[k * nx + (x < nx ? x : nx - 1)]);
+        size_t k = e / S.ldp;
+        int x = (int)(e % S.ldp);
+        const int xc = x < S.nx ? x : S.nx - 1;
+        double v = slowness_of(S.vel[k * S.nx + xc]);
+        long long bits = __double_as_longlong(v);
+        if (dist > 0 && (int)k >= dist) {
+            long long prev = __double_as_longlong(slowness_of(S.vel[(k - dist) * S.nx + xc]));
+            if (bits != prev) bits |= (long long)kSignBit;
+        }
+        slow[e] = __longlong_as_double(bits);
     }
+}
+
+// Thread 0 of a frequency workgroup, after a barrier that follows the stores of
+// the partial rows of block c: release them at agent scope and count.
+__device__ __forceinline__ void publish_block(const SecDev& S, int c)
+{
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(S.cnt + c, 1);
+    }
+}
+
+// Reducer workgroup q of a.nred: tasks q, q + nred, ... (ordered step-major
+// across sections, i.e. in production order).
+__device__ void reduce_role(const BatchArgs& a, int q, int* flag)
+{
+    int seen_sec = -1, seen_c = -1;
+    bool ok = true;
+    for (int i = q; i < a.ntasks; i += a.nred) {
+        const TaskDev T = task_of(a, i);
+        const SecDev S = sec_of(a, T.sec);
+        const int c = T.step / kPublish;
+        if (T.sec != seen_sec || c != seen_c) {
+            if (threadIdx.x == 0) {
+                int v, last = -1;
+                unsigned long long t0 = wall_clock64();
+                while ((v = __hip_atomic_load(S.cnt + c, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)) < S.nprod) {
+                    unsigned long long now = wall_clock64();
+                    if (v != last) {
+                        last = v;
+                        t0 = now;
+                    } else if (now - t0 > kStallTicks) {
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                __threadfence();
+                *flag = v >= S.nprod ? 1 : 0;
+            }
+            __syncthreads();
+            ok = *flag != 0;
+            __syncthreads();
+            seen_sec = T.sec;
+            seen_c = c;
+        }
+        const float* p = S.part + (size_t)T.step * S.nw * S.ldp;
+        double* row = S.rows + (size_t)T.step * S.nx;
+        for (int x0 = 2 * threadIdx.x; x0 < S.nx; x0 += 2 * blockDim.x) {
+            double a0 = 0.0, a1 = 0.0;
+            int r = 0;
+            for (; r + 8 <= S.nw; r += 8) {
+                float2 v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    v[j] = *reinterpret_cast<const float2*>(p + (size_t)(r + j) * S.ldp + x0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    a0 += (double)v[j].x;
+                    a1 += (double)v[j].y;
+                }
+            }
+            for (; r < S.nw; ++r) {
+                float2 v = *reinterpret_cast<const float2*>(p + (size_t)r * S.ldp + x0);
+                a0 += (double)v.x;
+                a1 += (double)v.y;
+            }
+            const double nan = __builtin_nan("");
+            row[x0] = ok ? a0 : nan;
+            if (x0 + 1 < S.nx) row[x0 + 1] = ok ? a1 : nan;
+        }
+    }
+}
+
+// Threads of a workgroup beyond its G sub-groups take no part in the work but
+// must meet every barrier of the active threads.
+__device__ __forceinline__ void idle_barriers(int n)
+{
+    for (int i = 0; i < n; ++i) __syncthreads();
 }
 
 struct Lane {
     int t, x0, LB, r;
-    bool ok0, ok1;
+    bool live, ok0, ok1;
     double ar;
 };
 
-// One depth step k: wait for this step's taps (issued during step k-1),
-// refill the other set for step k+1 where the slowness changed, prefetch the
-// slowness of step k+2, then the folded FIR, LDS write and partial row.
-// VMEM operations of a step are issued in a fixed order -- [refills], one
-// slowness load, [one partial-row store] -- so the wait at the top of the
-// next step has a static count that never includes that step's refills.
+// One depth step k with the current tap set.  All vector-memory operations
+// are issued first: the partial row of step k-1, refills of the other set for
+// step k+1 where the slowness changed, and the slowness prefetch for step
+// k+2; then the FIR.  The single wait at the top of the next step therefore
+// only covers operations issued a whole step earlier.
 template <int M, bool ROWS>
-__device__ __forceinline__ void step_fast(const ExtrapArgs& a, float2* sm, const Lane& L, int k,
-                                          float2 (&hc)[2][M + 1], float2 (&ho)[2][M + 1],
-                                          unsigned long long (&bo)[2], double2& sn, float2& o0,
+__device__ __forceinline__ void step_fast(const BatchArgs& a, const SecDev& S, float2* sm,
+                                          const Lane& L, int k, float2 (&hc)[2][M + 1],
+                                          float2 (&ho)[2][M + 1], double2& sn, float2& o0,
                                           float2& o1)
 {
-    wait_vmem<ROWS ? 1 : 0>();
-    if (k >= 1 && k + 1 < a.nsteps) {
-        unsigned long long u0 = dbits(sn.x), u1 = dbits(sn.y);
-        if (u0 != bo[0]) {
-            bo[0] = u0;
-            load_taps<M>(ho[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, sn.x) * (M + 1));
-        }
-        if (u1 != bo[1]) {
-            bo[1] = u1;
-            load_taps<M>(ho[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, sn.y) * (M + 1));
-        }
+    wait_vmem_all();
+    if (ROWS && k >= 1) {
+        float* pr = L.live ? S.part + ((size_t)(k - 1) * S.nw + L.r) * S.ldp + L.x0
+                           : a.trash + L.x0;
+        *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
     }
-    const int kp = k + 2 < a.nsteps ? k + 2 : a.nsteps - 1;
-    const double2 p = *reinterpret_cast<const double2*>(a.slow + (size_t)kp * a.ldp + L.x0);
+    // sn = slowness of step k+1, flagged where it differs from step k-1 (the
+    // step the other set was last loaded for)
+    if (k >= 1 && k + 1 < S.nsteps) {
+        if (slowness_changed(sn.x))
+            load_taps<M>(ho[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk,
+                                                                  slowness_value(sn.x)) * (M + 1));
+        if (slowness_changed(sn.y))
+            load_taps<M>(ho[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk,
+                                                                  slowness_value(sn.y)) * (M + 1));
+    }
+    const int kp = k + 2 < S.nsteps ? k + 2 : S.nsteps - 1;
+    const double2 p = *reinterpret_cast<const double2*>(S.slow + (size_t)kp * S.ldp + L.x0);
     fir2<M>(sm + (k & 1) * L.LB + 2 * L.t, hc[0], hc[1], o0, o1);
     float2* dst = sm + ((k + 1) & 1) * L.LB + M + L.x0;
     if (L.ok0) dst[0] = o0;
     if (L.ok1) dst[1] = o1;
-    if (ROWS) {
-        float* pr = a.part + ((size_t)k * a.nw + L.r) * a.ldp + L.x0;
-        *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
-    }
     sn = p;
     __syncthreads();
+    // the partial row of step k-1 is now stored by every thread
+    if (ROWS && k >= 1 && k % kPublish == 0) publish_block(S, (k - 1) / kPublish);
 }
 
-// Register-tap kernel.  Block = ceil(nx/2) threads rounded up to a wavefront;
-// LDS = two planes of 2*blockDim + 2M + 2 points, P[x] at offset M + x, zero
-// elsewhere (the zero boundary of Eq. 1).
+// Register-tap kernel, two outputs per thread.  Sub-group of tsub threads per
+// frequency; LDS per sub-group = two planes of 2*tsub + 2M + 2 points, P[x] at
+// offset M + x, zero elsewhere (the zero boundary of Eq. 1).
 template <int M, bool ROWS>
-__global__ void __launch_bounds__(512) k_extrap_fast(ExtrapArgs a)
+__global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
-    float2* sm = reinterpret_cast<float2*>(smem4);
+    if (ROWS && (int)blockIdx.x >= a.nitems) {
+        reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
+        return;
+    }
+    const ItemDev it = item_of(a, blockIdx.x);
+    const SecDev S = sec_of(a, it.sec);
+    int G, tsub;
+    group_shape(S, 1, G, tsub);
+    const int g = threadIdx.x / tsub;
     Lane L;
-    L.t = threadIdx.x;
-    L.r = blockIdx.x;
-    L.LB = 2 * blockDim.x + 2 * M + 2;
+    L.LB = 2 * tsub + 2 * M + 2;
+    if (g >= G) {
+        idle_barriers(2 + S.nsteps + (ROWS ? 1 : 0));
+        return;
+    }
+    float2* sm = reinterpret_cast<float2*>(smem4) + (size_t)g * 2 * L.LB;
+    L.t = threadIdx.x - g * tsub;
+    L.live = it.r0 + g < S.nw;
+    L.r = L.live ? it.r0 + g : S.nw - 1;
     L.x0 = 2 * L.t;
-    L.ok0 = L.x0 < a.nx;
-    L.ok1 = L.x0 + 1 < a.nx;
-    L.ar = a.omega[L.r] / a.dk;
+    L.ok0 = L.live && L.x0 < S.nx;
+    L.ok1 = L.live && L.x0 + 1 < S.nx;
+    L.ar = S.omega[L.r] / a.dk;
 
-    for (int i = L.t; i < 2 * L.LB; i += blockDim.x) sm[i] = make_float2(0.0f, 0.0f);
+    for (int i = L.t; i < 2 * L.LB; i += tsub) sm[i] = make_float2(0.0f, 0.0f);
     __syncthreads();
-    if (L.ok0) sm[M + L.x0] = a.win[(size_t)L.x0 * a.nw + L.r];
-    if (L.ok1) sm[M + L.x0 + 1] = a.win[(size_t)(L.x0 + 1) * a.nw + L.r];
+    if (L.ok0) sm[M + L.x0] = S.win[(size_t)L.x0 * S.nw + L.r];
+    if (L.ok1) sm[M + L.x0 + 1] = S.win[(size_t)(L.x0 + 1) * S.nw + L.r];
 
     float2 hA[2][M + 1], hB[2][M + 1];
-    unsigned long long bA[2], bB[2];
     {
-        const double2 s0 = *reinterpret_cast<const double2*>(a.slow + L.x0);
-        bA[0] = dbits(s0.x);
-        bA[1] = dbits(s0.y);
-        load_taps<M>(hA[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s0.x) * (M + 1));
-        load_taps<M>(hA[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s0.y) * (M + 1));
-        const int k1 = a.nsteps > 1 ? 1 : 0;
-        const double2 s1 = *reinterpret_cast<const double2*>(a.slow + (size_t)k1 * a.ldp + L.x0);
-        bB[0] = dbits(s1.x);
-        bB[1] = dbits(s1.y);
-        load_taps<M>(hB[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s1.x) * (M + 1));
-        load_taps<M>(hB[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, s1.y) * (M + 1));
+        const double2 s0 = *reinterpret_cast<const double2*>(S.slow + L.x0);
+        load_taps<M>(hA[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s0.x)) * (M + 1));
+        load_taps<M>(hA[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s0.y)) * (M + 1));
+        const int k1 = S.nsteps > 1 ? 1 : 0;
+        const double2 s1 = *reinterpret_cast<const double2*>(S.slow + (size_t)k1 * S.ldp + L.x0);
+        load_taps<M>(hB[0], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s1.x)) * (M + 1));
+        load_taps<M>(hB[1], a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s1.y)) * (M + 1));
     }
     double2 sn = make_double2(0.0, 0.0);
-    wait_vmem<0>();
     __syncthreads();
 
     float2 o0 = make_float2(0.0f, 0.0f), o1 = o0;
-    for (int k = 0; k < a.nsteps; k += 2) {
-        step_fast<M, ROWS>(a, sm, L, k, hA, hB, bB, sn, o0, o1);
-        if (k + 1 >= a.nsteps) break;
-        step_fast<M, ROWS>(a, sm, L, k + 1, hB, hA, bA, sn, o0, o1);
+    for (int k = 0; k < S.nsteps; k += 2) {
+        step_fast<M, ROWS>(a, S, sm, L, k, hA, hB, sn, o0, o1);
+        if (k + 1 >= S.nsteps) break;
+        step_fast<M, ROWS>(a, S, sm, L, k + 1, hB, hA, sn, o0, o1);
     }
-    if (a.wout) {
-        if (L.ok0) a.wout[(size_t)L.x0 * a.nw + L.r] = o0;
-        if (L.ok1) a.wout[(size_t)(L.x0 + 1) * a.nw + L.r] = o1;
+    if (ROWS) {
+        float* pr = L.live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + L.r) * S.ldp + L.x0
+                           : a.trash + L.x0;
+        *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
+        __syncthreads();
+        publish_block(S, (S.nsteps - 1) / kPublish);
+    }
+    if (S.wout) {
+        if (L.ok0) S.wout[(size_t)L.x0 * S.nw + L.r] = o0;
+        if (L.ok1) S.wout[(size_t)(L.x0 + 1) * S.nw + L.r] = o1;
     }
 }
 
@@ -228,126 +359,133 @@ __global__ void __launch_bounds__(512) k_extrap_fast(ExtrapArgs a)
 // thread and one tap set (two do not fit in 256 VGPRs), refilled at the end of
 // a step for outputs whose slowness changes at the next step.  A workgroup
 // touches only the table rows of its own frequency, so refills mostly hit in
-// L1 and the barrier covers part of their latency.
+// L1 and the barrier covers part of their latency.  One frequency per
+// workgroup.
 template <int M, bool ROWS>
-__global__ void __launch_bounds__(512) k_extrap_wide(ExtrapArgs a)
+__global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
+    if (ROWS && (int)blockIdx.x >= a.nitems) {
+        reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
+        return;
+    }
+    const ItemDev it = item_of(a, blockIdx.x);
+    const SecDev S = sec_of(a, it.sec);
+    int G, tsub;
+    group_shape(S, 2, G, tsub);
+    if ((int)threadIdx.x >= tsub) {
+        idle_barriers(2 + S.nsteps + (ROWS ? 1 : 0));
+        return;
+    }
     float2* sm = reinterpret_cast<float2*>(smem4);
-    const int t = threadIdx.x, r = blockIdx.x;
-    const int LB = 4 * blockDim.x + 2 * M + 4;
+    const int t = threadIdx.x;
+    const int LB = 4 * tsub + 2 * M + 4;
     const int x0 = 4 * t;
+    const bool live = it.r0 < S.nw;
+    const int r = live ? it.r0 : S.nw - 1;
     bool ok[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ok[q] = x0 + q < a.nx;
-    const double ar = a.omega[r] / a.dk;
+    for (int q = 0; q < 4; ++q) ok[q] = live && x0 + q < S.nx;
+    const double ar = S.omega[r] / a.dk;
 
-    for (int i = t; i < 2 * LB; i += blockDim.x) sm[i] = make_float2(0.0f, 0.0f);
+    for (int i = t; i < 2 * LB; i += tsub) sm[i] = make_float2(0.0f, 0.0f);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        if (ok[q]) sm[M + x0 + q] = a.win[(size_t)(x0 + q) * a.nw + r];
+        if (ok[q]) sm[M + x0 + q] = S.win[(size_t)(x0 + q) * S.nw + r];
 
     float2 h[4][M + 1];
-    unsigned long long bits[4];
-    double sn[4];
     {
-        const double2* s0 = reinterpret_cast<const double2*>(a.slow + x0);
-        const int k1 = a.nsteps > 1 ? 1 : 0;
-        const double2* s1 = reinterpret_cast<const double2*>(a.slow + (size_t)k1 * a.ldp + x0);
+        const double2* s0 = reinterpret_cast<const double2*>(S.slow + x0);
         double c[4] = {s0[0].x, s0[0].y, s0[1].x, s0[1].y};
-        double n1[4] = {s1[0].x, s1[0].y, s1[1].x, s1[1].y};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            bits[q] = dbits(c[q]);
-            load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, c[q]) * (M + 1));
-            sn[q] = n1[q];
-        }
+        for (int q = 0; q < 4; ++q)
+            load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, slowness_value(c[q])) * (M + 1));
     }
-    wait_vmem<0>();
     __syncthreads();
 
-    float2 o[4];
-    for (int k = 0; k < a.nsteps; ++k) {
-        const int kp = k + 2 < a.nsteps ? k + 2 : a.nsteps - 1;
-        const double2* sp = reinterpret_cast<const double2*>(a.slow + (size_t)kp * a.ldp + x0);
+    float2 o[4] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f),
+                   make_float2(0.0f, 0.0f)};
+    for (int k = 0; k < S.nsteps; ++k) {
+        wait_vmem_all();
+        if (ROWS && k >= 1) {
+            float* pr = live ? S.part + ((size_t)(k - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
+            *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
+        }
+        // slowness of step k+1 (flagged where it differs from step k), used
+        // after the FIR to refill taps
+        const int kp = k + 1 < S.nsteps ? k + 1 : S.nsteps - 1;
+        const double2* sp = reinterpret_cast<const double2*>(S.slow + (size_t)kp * S.ldp + x0);
         const double2 p01 = sp[0], p23 = sp[1];
         fir4<M>(sm + (k & 1) * LB + x0, h, o);
         float2* dst = sm + ((k + 1) & 1) * LB + M + x0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (ok[q]) dst[q] = o[q];
-        if (ROWS) {
-            float* pr = a.part + ((size_t)k * a.nw + r) * a.ldp + x0;
-            *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
-        }
-        if (k + 1 < a.nsteps) {
+        if (k + 1 < S.nsteps) {
+            const double sn[4] = {p01.x, p01.y, p23.x, p23.y};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                unsigned long long u = dbits(sn[q]);
-                if (u != bits[q]) {
-                    bits[q] = u;
-                    load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, sn[q]) * (M + 1));
-                }
-            }
+            for (int q = 0; q < 4; ++q)
+                if (slowness_changed(sn[q]))
+                    load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
+                                                                         slowness_value(sn[q])) * (M + 1));
         }
-        sn[0] = p01.x;
-        sn[1] = p01.y;
-        sn[2] = p23.x;
-        sn[3] = p23.y;
         __syncthreads();
+        if (ROWS && k >= 1 && k % kPublish == 0) publish_block(S, (k - 1) / kPublish);
     }
-    if (a.wout) {
+    if (ROWS) {
+        float* pr = live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
+        *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
+        __syncthreads();
+        publish_block(S, (S.nsteps - 1) / kPublish);
+    }
+    if (S.wout) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (ok[q]) a.wout[(size_t)(x0 + q) * a.nw + r] = o[q];
+            if (ok[q]) S.wout[(size_t)(x0 + q) * S.nw + r] = o[q];
     }
 }
 
-// General kernel: any M <= 31 and nx up to MIG_MAX_NX.  Same ownership (one
-// workgroup per frequency, plane in LDS), taps read from the table every step.
-__global__ void __launch_bounds__(256) k_extrap_general(ExtrapArgs a)
+// General kernel: any M <= 31 and nx up to MIG_MAX_NX.  One frequency per
+// workgroup, plane in LDS, taps read from the table every step.
+__global__ void __launch_bounds__(256) k_extrap_general(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
+    const bool rows_on = a.nred > 0;
+    if (rows_on && (int)blockIdx.x >= a.nitems) {
+        reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
+        return;
+    }
+    const ItemDev it = item_of(a, blockIdx.x);
+    const SecDev S = sec_of(a, it.sec);
     float2* sm = reinterpret_cast<float2*>(smem4);
-    const int M = a.M, nx = a.nx, r = blockIdx.x;
+    const int M = a.M, nx = S.nx;
+    const bool live = it.r0 < S.nw;
+    const int r = live ? it.r0 : S.nw - 1;
     const int LB = nx + 2 * M;
-    const double ar = a.omega[r] / a.dk;
+    const double ar = S.omega[r] / a.dk;
     for (int i = threadIdx.x; i < 2 * LB; i += blockDim.x) sm[i] = make_float2(0.0f, 0.0f);
     __syncthreads();
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) sm[M + x] = a.win[(size_t)x * a.nw + r];
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) sm[M + x] = S.win[(size_t)x * S.nw + r];
     __syncthreads();
-    for (int k = 0; k < a.nsteps; ++k) {
+    for (int k = 0; k < S.nsteps; ++k) {
         const float2* src = sm + (k & 1) * LB + M;
         float2* dst = sm + ((k + 1) & 1) * LB + M;
-        const double* sr = a.slow + (size_t)k * a.ldp;
+        const double* sr = S.slow + (size_t)k * S.ldp;
         for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const float2* h = a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, sr[x]) * (M + 1);
+            const float2* h = a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, slowness_value(sr[x])) * (M + 1);
             float2 acc = cmulf(h[0], src[x]);
             for (int n = 1; n <= M; ++n) acc = cfmaf(h[n], cadd(src[x - n], src[x + n]), acc);
             dst[x] = acc;
-            if (a.part) a.part[((size_t)k * a.nw + r) * a.ldp + x] = acc.x;
+            if (rows_on && live) S.part[((size_t)k * S.nw + r) * S.ldp + x] = acc.x;
         }
         __syncthreads();
+        if (rows_on && ((k + 1) % kPublish == 0 || k + 1 == S.nsteps))
+            publish_block(S, k / kPublish);
     }
-    if (a.wout) {
-        const float2* src = sm + (a.nsteps & 1) * LB + M;
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) a.wout[(size_t)x * a.nw + r] = src[x];
-    }
-}
-
-// rows[s][x] = sum_{r=0..nw-1} part[s][r][x], FP64, r in increasing order.
-__global__ void __launch_bounds__(256) k_rows_reduce(const float* __restrict__ part, int ldp,
-                                                     int nx, int nw, int nsteps,
-                                                     double* __restrict__ rows)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    for (int s = blockIdx.y; s < nsteps; s += gridDim.y) {
-        const float* p = part + (size_t)s * nw * ldp + x;
-        double acc = 0.0;
-        for (int r = 0; r < nw; ++r) acc += (double)p[(size_t)r * ldp];
-        rows[(size_t)s * nx + x] = acc;
+    if (S.wout && live) {
+        const float2* src = sm + (S.nsteps & 1) * LB + M;
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) S.wout[(size_t)x * S.nw + r] = src[x];
     }
 }
 
@@ -382,31 +520,34 @@ __global__ void k_index(const float* __restrict__ vel, const double* __restrict_
     }
 }
 
-template <int M>
-int launch_fast(const ExtrapArgs& a, hipStream_t s)
+__global__ void k_zero(int* p, int n)
 {
-    int threads = ((a.nx + 1) / 2 + 63) / 64 * 64;
-    size_t lds = (size_t)2 * (2 * threads + 2 * M + 2) * sizeof(float2);
-    if (a.part)
-        hipLaunchKernelGGL((k_extrap_fast<M, true>), dim3(a.nw), dim3(threads), lds, s, a);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+template <int M>
+int launch_fast(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
+{
+    if (a.nred > 0)
+        hipLaunchKernelGGL((k_extrap_fast<M, true>), dim3(a.nitems + a.nred), dim3(threads), lds,
+                           s, a);
     else
-        hipLaunchKernelGGL((k_extrap_fast<M, false>), dim3(a.nw), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_extrap_fast<M, false>), dim3(a.nitems), dim3(threads), lds, s, a);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
 template <int M>
-int launch_wide(const ExtrapArgs& a, hipStream_t s)
+int launch_wide(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
 {
-    int threads = ((a.nx + 3) / 4 + 63) / 64 * 64;
-    size_t lds = (size_t)2 * (4 * threads + 2 * M + 4) * sizeof(float2);
-    if (a.part)
-        hipLaunchKernelGGL((k_extrap_wide<M, true>), dim3(a.nw), dim3(threads), lds, s, a);
+    if (a.nred > 0)
+        hipLaunchKernelGGL((k_extrap_wide<M, true>), dim3(a.nitems + a.nred), dim3(threads), lds,
+                           s, a);
     else
-        hipLaunchKernelGGL((k_extrap_wide<M, false>), dim3(a.nw), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_extrap_wide<M, false>), dim3(a.nitems), dim3(threads), lds, s, a);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
-typedef int (*launch_fn)(const ExtrapArgs&, hipStream_t);
+typedef int (*launch_fn)(const BatchArgs&, int, size_t, hipStream_t);
 
 // Register-tap kernels are instantiated for N = 1..35 (M = 0..17); beyond
 // that two tap sets no longer fit in 256 VGPRs without spilling.
@@ -429,37 +570,56 @@ int extrap_kernel_kind(int nx, int M)
     return 0;
 }
 
-int launch_slowness(const float* vel, int nx, int nrows, int ldp, double* slow, hipStream_t s)
+int threads_per_omega(int kind, int nx)
 {
-    size_t total = (size_t)nrows * ldp;
-    size_t blocks = (total + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_slowness, dim3((unsigned)blocks), dim3(256), 0, s, vel, nx, nrows, ldp,
-                       slow);
+    if (kind == 1) return ((nx + 1) / 2 + 63) / 64 * 64;
+    if (kind == 2) return ((nx + 3) / 4 + 63) / 64 * 64;
+    return 256;
+}
+
+int launch_slowness(const BatchArgs& a, int max_rows, int max_ldp, int dist, hipStream_t s)
+{
+    size_t per = (size_t)max_rows * max_ldp;
+    size_t blocks = (per + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_slowness, dim3((unsigned)blocks, a.nsec), dim3(256), 0, s, a, dist);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
-int launch_extrap(const ExtrapArgs& a, hipStream_t s)
+int launch_extrap(const BatchArgs& a, int kind, int threads, hipStream_t s)
 {
-    int kind = extrap_kernel_kind(a.nx, a.M);
-    if (kind == 1) return kFast[a.M](a, s);
-    if (kind == 2) return kWide[a.M](a, s);
-    size_t lds = (size_t)2 * (a.nx + 2 * a.M) * sizeof(float2);
+    // LDS: G sub-groups x two planes; the host picks threads = G * tsub.
+    if (kind == 1) {
+        int tsub_min = 64;
+        size_t lds = (size_t)2 * (2 * threads + (threads / tsub_min) * (2 * a.M + 2)) * sizeof(float2);
+        return kFast[a.M](a, threads, lds, s);
+    }
+    if (kind == 2) {
+        size_t lds = (size_t)2 * (4 * threads + 2 * a.M + 4) * sizeof(float2);
+        return kWide[a.M](a, threads, lds, s);
+    }
+    return MIG_E_ARG;
+}
+
+int launch_general(const BatchArgs& a, int max_nx, hipStream_t s)
+{
+    size_t lds = (size_t)2 * (max_nx + 2 * a.M) * sizeof(float2);
     if (lds > 65536) {
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_extrap_general),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds) != hipSuccess)
             return MIG_E_DEVICE;
     }
-    hipLaunchKernelGGL(k_extrap_general, dim3(a.nw), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_extrap_general, dim3(a.nitems + a.nred), dim3(256), lds, s, a);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
-int launch_rows_reduce(const float* part, int ldp, int nx, int nw, int nsteps,
-                       double* rows, hipStream_t s)
+int launch_zero(int* p, int n, hipStream_t s)
 {
-    dim3 grid((nx + 255) / 256, nsteps < 65535 ? nsteps : 65535);
-    hipLaunchKernelGGL(k_rows_reduce, grid, dim3(256), 0, s, part, ldp, nx, nw, nsteps, rows);
+    int blocks = (n + 255) / 256;
+    if (blocks > 64) blocks = 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 

@@ -43,6 +43,23 @@ class CDesc(C.Structure):
     ]
 
 
+class CSection(C.Structure):
+    """ctypes mirror of ``mig_section``."""
+
+    _fields_ = [
+        ("data", C.c_void_p), ("vel", C.c_void_p), ("omega", C.c_void_p),
+        ("image", C.c_void_p),
+        ("nx", C.c_int32), ("nz", C.c_int32), ("nw", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class CTuning(C.Structure):
+    """ctypes mirror of ``mig_tuning``."""
+
+    _fields_ = [("omegas_per_group", C.c_int32), ("reducers", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
 def cdesc(d) -> CDesc:
     """Builds the C descriptor from any object with the TableDesc fields."""
     lam = d.lam if getattr(d, "lam", None) is not None else 1e-9 * d.ngrid
@@ -73,9 +90,12 @@ def lib():
         "mig_image": ([P, P, i32, i32, P], C.c_int),
         "mig_migrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
         "mig_kernel_kind": ([i32, i32], C.c_int),
+        "mig_batch_workspace_size": ([C.POINTER(CSection), i32, D, C.POINTER(CTuning)], sz),
+        "mig_migrate_batched": ([C.POINTER(CSection), i32, P, D, C.POINTER(CTuning), P, sz, P],
+                                C.c_int),
     }
     for name, (args, res) in sig.items():
-        f = getattr(L, name)
+        f = getattr(L, name)   # AttributeError: the built library is older than this binding
         f.argtypes = args
         f.restype = res
     _lib = L
@@ -167,7 +187,7 @@ def kernel_kind(nx, ntaps) -> int:
 
 
 def extrapolate(wf, vel, omega, tab32, desc, nsteps=None, rows=True, out=None, ws=None,
-                want_plane=True):
+                want_plane=True, rows_out=None):
     """A2-A4: advance wf [nx][nw] complex64 by nsteps (default vel.shape[0]).
 
     Returns (plane or None, rows [nsteps][nx] float64 or None)."""
@@ -184,7 +204,11 @@ def extrapolate(wf, vel, omega, tab32, desc, nsteps=None, rows=True, out=None, w
         out = torch.empty_like(wf)
     if out is not None:
         _need(out, torch.complex64, (nx, nw), "out")
-    rws = torch.empty((nsteps, nx), dtype=torch.float64, device=wf.device) if rows else None
+    if rows_out is not None:
+        _need(rows_out, torch.float64, (nsteps, nx), "rows_out")
+        rws = rows_out
+    else:
+        rws = torch.empty((nsteps, nx), dtype=torch.float64, device=wf.device) if rows else None
     if ws is None and nsteps > 0:
         ws = torch.empty(max(workspace_size(nx, nsteps, nw, desc), 1), dtype=torch.uint8,
                          device=wf.device)
@@ -199,8 +223,15 @@ def extrapolate(wf, vel, omega, tab32, desc, nsteps=None, rows=True, out=None, w
 def image(wf):
     """A3: row[x] = sum_r Re wf[x][r] (float64)."""
     nx, nw = wf.shape
-    _need(wf, torch.complex64, (nx, nw), "wf")
     row = torch.empty(nx, dtype=torch.float64, device=wf.device)
+    return image_into(wf, row)
+
+
+def image_into(wf, row):
+    """A3 into a caller-provided contiguous float64 row of length nx."""
+    nx, nw = wf.shape
+    _need(wf, torch.complex64, (nx, nw), "wf")
+    _need(row, torch.float64, (nx,), "row")
     _check(lib().mig_image(_p(wf), _p(row), nx, nw, _stream()), "mig_image")
     return row
 
@@ -224,3 +255,54 @@ def migrate(data, vel, omega, tab32, desc, ws=None, out=None):
                            _p(img), _p(ws), ws.numel(), _stream())
     _check(rc, "mig_migrate")
     return img
+
+
+def _sections(batch):
+    """batch: list of dicts with tensors data [nx][nw] c64, vel [nz][nx] f32,
+    omega [nw] f64 and image [nz][nx] f64 (allocated if missing)."""
+    arr = (CSection * len(batch))()
+    for i, b in enumerate(batch):
+        data, vel, omega = b["data"], b["vel"], b["omega"]
+        nx, nw = data.shape
+        nz = vel.shape[0]
+        _need(data, torch.complex64, (nx, nw), "data")
+        _need(vel, torch.float32, (nz, nx), "vel")
+        _need(omega, torch.float64, (nw,), "omega")
+        if b.get("image") is None:
+            b["image"] = torch.empty((nz, nx), dtype=torch.float64, device=data.device)
+        _need(b["image"], torch.float64, (nz, nx), "image")
+        arr[i] = CSection(data.data_ptr(), vel.data_ptr(), omega.data_ptr(),
+                          b["image"].data_ptr(), nx, nz, nw, 0)
+    return arr
+
+
+def _tuning(tune):
+    if tune is None:
+        return None
+    t = CTuning()
+    t.omegas_per_group = int(tune.get("omegas_per_group", 0))
+    t.reducers = int(tune.get("reducers", 0))
+    return C.byref(t)
+
+
+def batch_workspace_size(batch, desc, tune=None) -> int:
+    arr = _sections(batch)
+    cd = cdesc(desc)
+    return int(lib().mig_batch_workspace_size(arr, len(batch), C.byref(cd), _tuning(tune)))
+
+
+def migrate_batched(batch, tab32, desc, tune=None, ws=None):
+    """Batched Algorithm 1: every section's image (dict key "image") is filled.
+
+    tune: {"omegas_per_group": G, "reducers": R} or None (library defaults)."""
+    arr = _sections(batch)
+    _need(tab32, torch.complex64, (desc.nk, (desc.ntaps - 1) // 2 + 1), "tab32")
+    cd = cdesc(desc)
+    tn = _tuning(tune)
+    if ws is None:
+        n = int(lib().mig_batch_workspace_size(arr, len(batch), C.byref(cd), tn))
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=tab32.device)
+    rc = lib().mig_migrate_batched(arr, len(batch), _p(tab32), C.byref(cd), tn, _p(ws),
+                                   ws.numel(), _stream())
+    _check(rc, "mig_migrate_batched")
+    return [b["image"] for b in batch]

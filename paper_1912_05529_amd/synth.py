@@ -251,6 +251,43 @@ def random_case(seed: int, nx: int, nz: int, nw: int, ntaps: int = 25, nk: int =
                    extra={"seed": seed})
 
 
+# --------------------------------------------------------------------------- #
+# Configuration 3: a batch of independent sections of uneven size.
+# --------------------------------------------------------------------------- #
+def bandlimited_data(rng: np.random.Generator, nx: int, nw: int, dx: float,
+                     kx_max: float) -> np.ndarray:
+    """Random complex f-x plane whose lateral spectrum is confined to
+    |kx| <= kx_max (rad/m): white Gaussian spectra, zeroed outside the band,
+    transformed back along x.  [nx][nw] complex128."""
+    spec = rng.standard_normal((nx, nw)) + 1j * rng.standard_normal((nx, nw))
+    kx = TWO_PI * np.fft.fftfreq(nx, d=dx)
+    spec[np.abs(kx) > kx_max] = 0.0
+    return np.fft.ifft(spec, axis=0)
+
+
+def config3(seed: int = 3, nsec: int = 64, nx_range=(256, 2048), nz_range=(200, 800),
+            nw_range=(100, 300), dx: float = 10.0, dz: float = 10.0, fmin: float = 5.0,
+            fmax: float = 55.0, ntaps: int = 35, nk: int = 2048) -> list:
+    """Batch of `nsec` sections with seed-drawn nx, nz, nw (inclusive ranges),
+    velocity models drawn like configuration 2, and band-limited random
+    complex data (propagating band of the slowest medium at fmax), all
+    sharing configuration 2's table."""
+    rng = np.random.default_rng(seed)
+    desc = table_for(ntaps, nk, fmin, fmax, 750.0, 2400.0, dx, dz)
+    out = []
+    for i in range(nsec):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        nz = int(rng.integers(nz_range[0], nz_range[1] + 1))
+        nw = int(rng.integers(nw_range[0], nw_range[1] + 1))
+        v = layered_model(rng, nx, nz, dx, dz)
+        vel = (v / 2.0).astype(np.float32)
+        om = omegas(nw, fmin, fmax)
+        data = bandlimited_data(rng, nx, nw, dx, TWO_PI * fmax / 750.0)
+        out.append(Section("config3_%02d" % i, nx, nz, dx, dz, om, vel, data, desc,
+                           extra={"seed": seed, "index": i}))
+    return out
+
+
 def with_desc(sec: Section, **kw) -> Section:
     sec.desc = replace(sec.desc, **kw)
     return sec

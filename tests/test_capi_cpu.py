@@ -79,11 +79,11 @@ def test_workspace_sizes_and_kernel_kinds(L):
     d = _desc(ntaps=35, nk=2048)
     full = mig.workspace_size(1024, 511, 200, d)
     one = mig.workspace_min_size(1024, 200, d)
-    plane = 1024 * 200 * 8
+    plane = 1024 * 200 * 8 + 16384 + 1024 * 4  # scratch plane + block counters + sink row
     step = 1024 * 8 + 200 * 1024 * 4          # slowness row + partial rows
     assert one == plane + step
     assert full == plane + 511 * step
-    plane_1000 = (1000 * 7 * 8 + 255) // 256 * 256
+    plane_1000 = (1000 * 7 * 8 + 255) // 256 * 256 + 16384 + 1024 * 4
     assert mig.workspace_size(1000, 3, 7, d) == plane_1000 + 3 * (1024 * 8 + 7 * 1024 * 4)
     assert mig.kernel_kind(1024, 35) == 1
     assert mig.kernel_kind(1025, 35) == 2

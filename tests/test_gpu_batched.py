@@ -1,0 +1,103 @@
+"""Batched form (many sections, one launch per kernel variant) through the C ABI.
+
+The batched entry point is a scheduling form of the same computation: each
+frequency of each section runs the same instructions as in mig_migrate and the
+image sums over frequencies keep their order, so per-section images must be
+bit-identical to mig_migrate's whatever the tuning knobs; parity with the FP64
+oracle follows from that and is checked directly on a small batch too.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1912_05529_amd import mig, synth
+from gpu_helpers import data64, dev, rel_l2, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(shapes, seed=50, ntaps=35):
+    secs = []
+    for i, (nx, nz, nw, layered) in enumerate(shapes):
+        secs.append(synth.random_case(seed + i, nx, nz, nw, ntaps=ntaps, nk=256, layered=layered))
+    desc = secs[0].desc
+    for s in secs:
+        s.desc = desc
+    return secs, desc
+
+
+SHAPES = [
+    # nx, nz, nw, layered: kinds 1, 1 (G>1), 2, 0 (nx > 2048), nz = 1, nz = 2
+    (300, 40, 13, True),
+    (100, 25, 9, False),
+    (1500, 20, 5, True),
+    (2100, 9, 3, False),
+    (64, 1, 4, True),
+    (700, 2, 6, False),
+]
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    secs, desc = _batch(SHAPES)
+    tab = mig.design_table(desc, dev())
+    return secs, desc, tab
+
+
+def _run_batched(secs, desc, tab, tune=None):
+    batch = [dict(upload(s)) for s in secs]
+    mig.migrate_batched(batch, tab["tab32"], desc, tune=tune)
+    torch.cuda.synchronize()
+    return [b["image"].cpu().numpy() for b in batch]
+
+
+def test_batched_equals_per_section_migrate(mixed):
+    secs, desc, tab = mixed
+    print("kinds", [mig.kernel_kind(s.nx, desc.ntaps) for s in secs], flush=True)
+    got = _run_batched(secs, desc, tab)
+    for s, g in zip(secs, got):
+        t = upload(s)
+        ref = mig.migrate(t["data"], t["vel"], t["omega"], tab["tab32"], desc).cpu().numpy()
+        assert np.array_equal(g, ref), s.name
+
+
+@pytest.mark.parametrize("tune", [{"omegas_per_group": 1, "reducers": 8},
+                                  {"omegas_per_group": 2, "reducers": 33},
+                                  {"omegas_per_group": 4, "reducers": 64}])
+def test_batched_tuning_does_not_change_results(mixed, tune):
+    secs, desc, tab = mixed
+    base = _run_batched(secs, desc, tab)
+    got = _run_batched(secs, desc, tab, tune)
+    for a, b in zip(base, got):
+        assert np.array_equal(a, b)
+
+
+def test_batched_matches_oracle(mixed):
+    secs, desc, tab = mixed
+    ot = oracle.design_table(desc)[0]
+    got = _run_batched(secs, desc, tab)
+    for s, g in zip(secs, got):
+        ref = oracle.migrate(desc, ot, s.omega, s.vel, data64(s))
+        assert rel_l2(g, ref) <= 1e-5, s.name
+
+
+def test_batched_workspace_and_argument_errors(mixed):
+    secs, desc, tab = mixed
+    batch = [dict(upload(s)) for s in secs]
+    small = torch.empty(1024, dtype=torch.uint8, device=dev())
+    with pytest.raises(mig.MigError) as e:
+        mig.migrate_batched(batch, tab["tab32"], desc, ws=small)
+    assert e.value.code == mig.MIG_E_WORKSPACE
+    with pytest.raises(mig.MigError) as e:
+        mig.migrate_batched(batch, tab["tab32"], desc, tune={"omegas_per_group": -1})
+    assert e.value.code == mig.MIG_E_ARG
+
+
+def test_autotuner_picks_a_measured_candidate(mixed):
+    from paper_1912_05529_amd import tune as tuner
+    secs, desc, tab = mixed
+    batch = [dict(upload(s)) for s in secs]
+    best, table = tuner.autotune(batch, tab["tab32"], desc, reps=1)
+    assert best in [row["tune"] for row in table]
+    assert all(row["ms"] > 0 for row in table)

@@ -188,3 +188,22 @@ def test_extrapolate_zero_steps_and_errors(tables):
     with pytest.raises(mig.MigError) as e:
         mig.extrapolate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc, 2, ws=small)
     assert e.value.code == mig.MIG_E_WORKSPACE
+
+
+@pytest.mark.parametrize("nx,nw,nsteps", [(1024, 600, 20), (130, 37, 33), (2000, 9, 17)])
+def test_fused_reduction_rows_match_oracle(nx, nw, nsteps, tables):
+    """Image rows formed inside the depth-stepping launch (reducer workgroups)
+    for more frequency workgroups than CUs, for several publish blocks with a
+    ragged last block, and for the four-outputs-per-thread kernel."""
+    sec = synth.random_case(3000 + nx + nw, nx, nsteps + 1, nw, ntaps=35, nk=256)
+    (ot, _, _, _), g = tables(sec.desc)
+    print("fused rows nx=%d nw=%d nsteps=%d kind=%d" % (nx, nw, nsteps, mig.kernel_kind(nx, 35)),
+          flush=True)
+    t = upload(sec)
+    vel = t["vel"][:nsteps].contiguous()
+    _, rows = mig.extrapolate(t["data"], vel, t["omega"], g["tab32"], sec.desc, nsteps,
+                              want_plane=False)
+    r = rows.cpu().numpy()
+    assert np.isfinite(r).all()
+    _, ref = oracle.extrapolate(sec.desc, ot, sec.omega, sec.vel[:nsteps], data64(sec), nsteps)
+    assert rel_l2(r, ref) <= 1e-5
