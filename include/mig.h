@@ -205,6 +205,44 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel,
                         void* stream);
 
 /*
+ * The step before the depth loop (Algorithm 1: transform of the section along
+ * t; Sec. III): out[x][r] = sum_n section[x][n] exp(-i omega_r n dt), directly
+ * at the given frequencies (they need not be FFT bins), so that t-x sections
+ * can be migrated.  A dense contraction section [nx][nt] x DFT matrix, run on
+ * the matrix cores in FP32 (the DFT matrix is formed in FP64 and rounded).
+ *   section [nx][nt] float32 (in), omega [nw] float64 (in),
+ *   out [nx][nw] complex64 (out), ws >= mig_transform_workspace_size bytes.
+ */
+MIG_API size_t mig_transform_workspace_size(int32_t nt, int32_t nw);
+MIG_API int mig_transform_t(const float* section, int32_t nx, int32_t nt,
+                            double dt, const double* omega, int32_t nw,
+                            mig_c64* out, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * Adjoint of mig_migrate (demigration / exploding-reflector modelling), for
+ * least-squares migration and gradients.  With the real inner product
+ * <a, b> = Re sum conj(a) b on planes and the ordinary one on images, it is the
+ * exact transpose of the linear map data -> image of Algorithm 1 (same
+ * filters, same look-up, same zero boundary):
+ *     Q_{nz-1}[x][r] = image[nz-1][x],
+ *     Q_k[x][r] = image[k][x] + sum_{n=-M..M} conj(h_{j(x+n,k)}[|n|]) Q_{k+1}[x+n][r],
+ *     data = Q_0,
+ * where j(x, k) is the table entry of (omega_r, vel[k][x]).  FP32 complex
+ * arithmetic, one workgroup per frequency walking the depth steps backwards.
+ *   image [nz][nx] float64 (in), vel [nz][nx] float32 (in; row nz-1 unused),
+ *   omega [nw] float64 (in), tab32 [nk][M+1] complex64 (in),
+ *   data  [nx][nw] complex64 (out), ws >= mig_demigrate_workspace_size bytes.
+ */
+MIG_API size_t mig_demigrate_workspace_size(int32_t nx, int32_t nz,
+                                            const mig_table_desc* d);
+MIG_API int mig_demigrate(const double* image, const float* vel,
+                          const double* omega, const mig_c64* tab32,
+                          const mig_table_desc* d, int32_t nx, int32_t nz,
+                          int32_t nw, mig_c64* data, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
  * Batched form: many independent 2-D sections (different nx, nz, nw, all
  * sharing one table) migrated in at most three launches -- one per kernel
  * variant -- instead of one per section.  Every section is Algorithm 1 end to

@@ -18,6 +18,8 @@ Functions follow the paper (Shawahna, Salam & Al-Mouhamed, arXiv 1912.05529):
 * :func:`image` -- depth row = Re of the sum over frequencies (Algorithm 1).
 * :func:`migrate` -- Algorithm 1 end to end on an f-x section.
 * :func:`demigrate` -- exact adjoint of :func:`migrate`.
+* :func:`transform_t` -- the transform along t that precedes the depth loop
+  (Algorithm 1, first step), evaluated directly at the requested frequencies.
 
 Parity status: every function above is pinned by a CPU test against a closed
 form, a textbook routine, an invariant or brute force (``tests/test_oracle_*``).
@@ -33,4 +35,5 @@ from .core import (  # noqa: F401
     migrate,
     num_threads,
     table_index,
+    transform_t,
 )

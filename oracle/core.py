@@ -97,8 +97,10 @@ def load():
     lib.orc_migrate.argtypes = [D, P, P, i32, P, i32, i32, P, P]
     lib.orc_demigrate.argtypes = [D, P, P, i32, P, i32, i32, P, P]
     lib.orc_num_threads.argtypes = []
+    lib.orc_transform_t.argtypes = [P, i32, i32, C.c_double, P, i32, P]
     for f in ("orc_design_table", "orc_table_index", "orc_extrapolate",
-              "orc_image", "orc_migrate", "orc_demigrate", "orc_num_threads"):
+              "orc_image", "orc_migrate", "orc_demigrate", "orc_num_threads",
+              "orc_transform_t"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -216,3 +218,14 @@ def demigrate(desc, tab, omega, vel, img):
     _check(load().orc_demigrate(C.byref(cd), _ptr(tab), _ptr(omega), nw, _ptr(vel), nx, nz,
                                 _ptr(img), _ptr(data)), "demigrate")
     return data
+
+
+def transform_t(section, dt, omega):
+    """section [nx][nt] float32 -> [nx][nw] complex128 (direct DFT at omega)."""
+    section = _f32(section)
+    omega = _f64(omega)
+    nx, nt = section.shape
+    out = np.zeros((nx, omega.size), np.complex128)
+    _check(load().orc_transform_t(_ptr(section), nx, nt, float(dt), _ptr(omega), omega.size,
+                                  _ptr(out)), "transform_t")
+    return out

@@ -387,3 +387,25 @@ int orc_demigrate(const orc_desc* d, const double* tab, const double* omega,
     free(Q); free(R);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Transform along t (Algorithm 1: "Fourier transform of shot gather along  */
+/* t-axis"; Sec. III), evaluated directly at the requested frequencies with */
+/* the forward sign exp(-i omega t).                                        */
+/* ------------------------------------------------------------------------ */
+int orc_transform_t(const float* p, int32_t nx, int32_t nt, double dt,
+                    const double* omega, int32_t nw, double* out)
+{
+    if (!p || !omega || !out || nx < 1 || nt < 1 || nw < 1 || !(dt > 0.0)) return ORC_E_ARG;
+#pragma omp parallel for schedule(static)
+    for (int x = 0; x < nx; ++x) {
+        for (int r = 0; r < nw; ++r) {
+            cplx acc = 0.0;
+            for (int n = 0; n < nt; ++n)
+                acc += (double)p[(size_t)x * nt + n] * cexp(-I * (omega[r] * ((double)n * dt)));
+            out[2 * ((size_t)x * nw + r)] = creal(acc);
+            out[2 * ((size_t)x * nw + r) + 1] = cimag(acc);
+        }
+    }
+    return ORC_OK;
+}

@@ -93,6 +93,12 @@ int orc_demigrate(const orc_desc* d, const double* tab, const double* omega,
                   int32_t nw, const float* vel, int32_t nx, int32_t nz,
                   const double* image, double* data);
 
+/* Transform along t (Algorithm 1, first step; Sec. III): for a section
+ * p[nx][nt] sampled at dt, out[x][r] = sum_n p[x][n] exp(-i omega_r n dt),
+ * complex [nx][nw] (interleaved doubles), at arbitrary frequencies. */
+int orc_transform_t(const float* p, int32_t nx, int32_t nt, double dt,
+                    const double* omega, int32_t nw, double* out);
+
 /* Number of OpenMP threads the oracle will use. */
 int orc_num_threads(void);
 

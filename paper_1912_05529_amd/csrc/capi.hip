@@ -499,6 +499,80 @@ MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec, const mig
                      as_stream(stream));
 }
 
+MIG_API size_t mig_demigrate_workspace_size(int32_t nx, int32_t nz, const mig_table_desc* d)
+{
+    if (!desc_valid(d) || nx < 1 || nx > MIG_MAX_NX || nz < 1) return 0;
+    size_t rows = nz > 1 ? (size_t)(nz - 1) : 1;
+    return align_up(rows * row_stride(nx) * sizeof(double), kAlign);
+}
+
+MIG_API int mig_demigrate(const double* image, const float* vel, const double* omega,
+                          const mig_c64* tab32, const mig_table_desc* d, int32_t nx, int32_t nz,
+                          int32_t nw, mig_c64* data, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!desc_valid(d) || !image || !vel || !omega || !tab32 || !data || !sizes_ok(nx, nw) ||
+        nz < 1)
+        return MIG_E_ARG;
+    const size_t need = mig_demigrate_workspace_size(nx, nz, d);
+    if (!ws || ws_bytes < need) return MIG_E_WORKSPACE;
+    if (overlap(ws, ws_bytes, data, (size_t)nx * nw * sizeof(mig_c64))) return MIG_E_ARG;
+    int dev = 0, lds_max = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 65536;
+    const int M = (d->ntaps - 1) / 2;
+    AdjArgs a = {};
+    a.chunk = adjoint_chunk(nx, M, (size_t)lds_max);
+    if (a.chunk < 1) return MIG_E_ARG;
+    hipStream_t s = as_stream(stream);
+    a.image = image;
+    a.slow = static_cast<const double*>(ws);
+    a.omega = omega;
+    a.tab = reinterpret_cast<const float2*>(tab32);
+    a.out = reinterpret_cast<float2*>(data);
+    a.nx = nx;
+    a.nz = nz;
+    a.nw = nw;
+    a.ldp = row_stride(nx);
+    a.nk = d->nk;
+    a.M = M;
+    a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
+    a.b = d->kmin / a.dk;
+    if (nz > 1) {
+        BatchArgs sa = {};
+        sa.nsec = 1;
+        sa.one.vel = vel;
+        sa.one.slow = a.slow;
+        sa.one.nx = nx;
+        sa.one.nsteps = nz - 1;
+        sa.one.ldp = a.ldp;
+        int rc = launch_slowness(sa, nz - 1, a.ldp, 0, s);
+        if (rc != MIG_OK) return rc;
+    }
+    return launch_demigrate(a, s);
+}
+
+MIG_API size_t mig_transform_workspace_size(int32_t nt, int32_t nw)
+{
+    if (nt < 1 || nw < 1 || nw > MIG_MAX_NW) return 0;
+    return align_up((size_t)nt * 2 * nw * sizeof(float), kAlign);
+}
+
+MIG_API int mig_transform_t(const float* section, int32_t nx, int32_t nt, double dt,
+                            const double* omega, int32_t nw, mig_c64* out, void* ws,
+                            size_t ws_bytes, void* stream)
+{
+    if (!section || !omega || !out || !sizes_ok(nx, nw) || nt < 1 || !(dt > 0.0))
+        return MIG_E_ARG;
+    const size_t need = mig_transform_workspace_size(nt, nw);
+    if (!ws || ws_bytes < need) return MIG_E_WORKSPACE;
+    if (overlap(section, (size_t)nx * nt * sizeof(float), out, (size_t)nx * nw * sizeof(mig_c64)) ||
+        overlap(ws, ws_bytes, out, (size_t)nx * nw * sizeof(mig_c64)))
+        return MIG_E_ARG;
+    return launch_transform(section, nx, nt, dt, omega, nw, reinterpret_cast<float2*>(out),
+                            static_cast<float*>(ws), as_stream(stream));
+}
+
 // Internal query used by tests and the benchmark: which extrapolation kernel
 // a call with these sizes takes (1 = register-tap kernel, 0 = general).
 MIG_API int mig_kernel_kind(int32_t nx, int32_t ntaps)

@@ -58,6 +58,18 @@ struct BatchArgs {
     double b;              // kmin / dk
 };
 
+// Arguments of the demigration (adjoint) launch: one workgroup per frequency.
+struct AdjArgs {
+    const double* image;   // [nz][nx] image rows (input)
+    const double* slow;    // [nz-1][ldp] slowness rows of the depth steps
+    const double* omega;   // [nw]
+    const float2* tab;     // [nk][M+1]
+    float2* out;           // [nx][nw] surface plane (output)
+    int nx, nz, nw, ldp, nk, M;
+    int chunk;             // filter taps handled per LDS pass
+    double dk, b;
+};
+
 // Slowness used by the table look-up: 1/v as an IEEE double division, or NaN
 // when v is not > 0 (which selects entry 0).
 __device__ __forceinline__ double slowness_of(float v)
@@ -131,6 +143,13 @@ inline int flag_distance(int kind) { return kind == 1 ? 2 : (kind == 2 ? 1 : 0);
 int launch_extrap(const BatchArgs& a, int kind, int threads, hipStream_t s);
 int launch_general(const BatchArgs& a, int max_nx, hipStream_t s);
 int launch_zero(int* p, int n, hipStream_t s);
+// Taps per LDS pass of the demigration kernel for an LDS budget (0 = too big).
+int adjoint_chunk(int nx, int M, size_t lds_limit);
+int launch_demigrate(const AdjArgs& a, hipStream_t s);
+// Transform along t: builds the FP32 DFT matrix B [nt][2 nw] and computes the
+// plane out [nx][nw] = section [nx][nt] . B on the matrix cores.
+int launch_transform(const float* section, int nx, int nt, double dt, const double* omega,
+                     int nw, float2* out, float* B, hipStream_t s);
 int launch_image(const float2* wf, double* row, int nx, int nw, hipStream_t s);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

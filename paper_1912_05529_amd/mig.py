@@ -90,6 +90,10 @@ def lib():
         "mig_image": ([P, P, i32, i32, P], C.c_int),
         "mig_migrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
         "mig_kernel_kind": ([i32, i32], C.c_int),
+        "mig_transform_workspace_size": ([i32, i32], sz),
+        "mig_transform_t": ([P, i32, i32, C.c_double, P, i32, P, P, sz, P], C.c_int),
+        "mig_demigrate_workspace_size": ([i32, i32, D], sz),
+        "mig_demigrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
         "mig_batch_workspace_size": ([C.POINTER(CSection), i32, D, C.POINTER(CTuning)], sz),
         "mig_migrate_batched": ([C.POINTER(CSection), i32, P, D, C.POINTER(CTuning), P, sz, P],
                                 C.c_int),
@@ -306,3 +310,52 @@ def migrate_batched(batch, tab32, desc, tune=None, ws=None):
                                    ws.numel(), _stream())
     _check(rc, "mig_migrate_batched")
     return [b["image"] for b in batch]
+
+
+def demigrate_workspace_size(nx, nz, desc) -> int:
+    cd = cdesc(desc)
+    return int(lib().mig_demigrate_workspace_size(nx, nz, C.byref(cd)))
+
+
+def demigrate(image, vel, omega, tab32, desc, nw=None, out=None, ws=None):
+    """Adjoint of migrate: image [nz][nx] float64 -> surface plane [nx][nw] complex64."""
+    nz, nx = image.shape
+    nw = omega.numel() if nw is None else nw
+    _need(image, torch.float64, (nz, nx), "image")
+    _need(vel, torch.float32, (nz, nx), "vel")
+    _need(omega, torch.float64, (nw,), "omega")
+    _need(tab32, torch.complex64, (desc.nk, (desc.ntaps - 1) // 2 + 1), "tab32")
+    if out is None:
+        out = torch.empty((nx, nw), dtype=torch.complex64, device=image.device)
+    _need(out, torch.complex64, (nx, nw), "data")
+    if ws is None:
+        ws = torch.empty(max(demigrate_workspace_size(nx, nz, desc), 1), dtype=torch.uint8,
+                         device=image.device)
+    cd = cdesc(desc)
+    rc = lib().mig_demigrate(_p(image), _p(vel), _p(omega), _p(tab32), C.byref(cd), nx, nz, nw,
+                             _p(out), _p(ws), ws.numel(), _stream())
+    _check(rc, "mig_demigrate")
+    return out
+
+
+def transform_t(section, dt, omega, out=None, ws=None):
+    """Transform along t: section [nx][nt] float32 -> plane [nx][nw] complex64."""
+    nx, nt = section.shape
+    nw = omega.numel()
+    _need(section, torch.float32, (nx, nt), "section")
+    _need(omega, torch.float64, (nw,), "omega")
+    if out is None:
+        out = torch.empty((nx, nw), dtype=torch.complex64, device=section.device)
+    _need(out, torch.complex64, (nx, nw), "out")
+    if ws is None:
+        n = int(lib().mig_transform_workspace_size(nt, nw))
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=section.device)
+    rc = lib().mig_transform_t(_p(section), nx, nt, float(dt), _p(omega), nw, _p(out), _p(ws),
+                               ws.numel(), _stream())
+    _check(rc, "mig_transform_t")
+    return out
+
+
+def migrate_tx(section, dt, vel, omega, tab32, desc, ws=None):
+    """Algorithm 1 from a t-x section: transform along t, then migrate."""
+    return migrate(transform_t(section, dt, omega), vel, omega, tab32, desc, ws=ws)

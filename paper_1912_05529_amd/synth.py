@@ -137,7 +137,7 @@ def config1(seed: int = 1, nx: int = 128, nz: int = 128, nw: int = 64,
     desc = table_for(ntaps, nk, fmin, fmax, v_prop, v_prop, dx, dz)
     return Section("config1_diffraction", nx, nz, dx, dz, om, vel, data, desc,
                    extra={"ix0": ix0, "iz0": iz0, "nt": nt, "dt": dt,
-                          "seed": seed})
+                          "seed": seed, "section": p.astype(np.float32)})
 
 
 # --------------------------------------------------------------------------- #
