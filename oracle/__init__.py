@@ -18,6 +18,8 @@ Functions follow the paper (Shawahna, Salam & Al-Mouhamed, arXiv 1912.05529):
 * :func:`image` -- depth row = Re of the sum over frequencies (Algorithm 1).
 * :func:`migrate` -- Algorithm 1 end to end on an f-x section.
 * :func:`demigrate` -- exact adjoint of :func:`migrate`.
+* :func:`design_table_2d`, :func:`migrate3d` -- the 3-D extension (Sec. II):
+  circularly symmetric 2-D extrapolators and the 2-D form of Eq. (1).
 * :func:`transform_t` -- the transform along t that precedes the depth loop
   (Algorithm 1, first step), evaluated directly at the requested frequencies.
 
@@ -29,10 +31,12 @@ from .core import (  # noqa: F401
     build,
     demigrate,
     design_table,
+    design_table_2d,
     extrapolate,
     image,
     load,
     migrate,
+    migrate3d,
     num_threads,
     table_index,
     transform_t,

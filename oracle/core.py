@@ -98,9 +98,11 @@ def load():
     lib.orc_demigrate.argtypes = [D, P, P, i32, P, i32, i32, P, P]
     lib.orc_num_threads.argtypes = []
     lib.orc_transform_t.argtypes = [P, i32, i32, C.c_double, P, i32, P]
+    lib.orc_design_table_2d.argtypes = [D, C.c_int, P, P, P, P]
+    lib.orc_migrate3d.argtypes = [D, P, P, i32, P, i32, i32, i32, P, P]
     for f in ("orc_design_table", "orc_table_index", "orc_extrapolate",
               "orc_image", "orc_migrate", "orc_demigrate", "orc_num_threads",
-              "orc_transform_t"):
+              "orc_transform_t", "orc_design_table_2d", "orc_migrate3d"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -229,3 +231,35 @@ def transform_t(section, dt, omega):
     _check(load().orc_transform_t(_ptr(section), nx, nt, float(dt), _ptr(omega), omega.size,
                                   _ptr(out)), "transform_t")
     return out
+
+
+def design_table_2d(desc, apply_scale: bool = True):
+    """2-D circularly symmetric table: (tab [nk][NU] complex128, maxgain, passerr, scale)."""
+    d = OrcDesc.from_obj(desc) if not isinstance(desc, OrcDesc) else desc
+    M = (d.ntaps - 1) // 2
+    NU = (M + 1) * (M + 2) // 2
+    tab = np.zeros((d.nk, NU), np.complex128)
+    mg = np.zeros(d.nk)
+    pe = np.zeros(d.nk)
+    sc = np.zeros(d.nk)
+    cd = d.c()
+    _check(load().orc_design_table_2d(C.byref(cd), int(bool(apply_scale)), _ptr(tab), _ptr(mg),
+                                      _ptr(pe), _ptr(sc)), "design_table_2d")
+    return tab, mg, pe, sc
+
+
+def migrate3d(desc, tab, omega, vel, data):
+    """data [nx][ny][nw] complex, vel [nz][nx][ny] -> image [nz][nx][ny]."""
+    d = OrcDesc.from_obj(desc) if not isinstance(desc, OrcDesc) else desc
+    tab = _c128(tab)
+    omega = _f64(omega)
+    vel = _f32(vel)
+    data = _c128(data)
+    nx, ny, nw = data.shape
+    nz = vel.shape[0]
+    assert vel.shape == (nz, nx, ny) and omega.size == nw
+    img = np.zeros((nz, nx, ny))
+    cd = d.c()
+    _check(load().orc_migrate3d(C.byref(cd), _ptr(tab), _ptr(omega), nw, _ptr(vel), nx, ny, nz,
+                                _ptr(data), _ptr(img)), "migrate3d")
+    return img

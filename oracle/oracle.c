@@ -409,3 +409,211 @@ int orc_transform_t(const float* p, int32_t nx, int32_t nt, double dt,
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* 3-D extension (Sec. II: explicit f-x migration extends to 3-D with 2-D   */
+/* filters; Eq. (1) becomes a 2-D convolution per frequency).               */
+/*                                                                          */
+/* Design: the 2-D analogue of design_one.  Target on the midpoint grid of  */
+/* (theta_x, theta_y) in (0, pi)^2:                                         */
+/*   D = exp(+i zeta sqrt(kappa^2 - r^2)) for r <= kappa, else              */
+/*       exp(-zeta sqrt(r^2 - kappa^2)),   r^2 = theta_x^2 + theta_y^2,     */
+/* weights by r as in 1-D.  Basis per unique coefficient (a, b): the sum of */
+/* cos(n1 theta_x) cos(n2 theta_y) over the symmetry orbit of (a, b), i.e.  */
+/*   1                                              a = b = 0               */
+/*   2 (cos a tx + cos a ty)                        a > 0, b = 0            */
+/*   4 cos a tx cos a ty                            a = b > 0               */
+/*   4 (cos a tx cos b ty + cos b tx cos a ty)      a > b > 0               */
+/* Stability: applying the 1-D Bernstein bound along each axis,             */
+/* |H|max <= max_grid |H| / cos(M pi / (2 Lc))^2.                           */
+/* ------------------------------------------------------------------------ */
+static double basis2d(int a, int b, double tx, double ty)
+{
+    if (a == 0) return 1.0;
+    if (b == 0) return 2.0 * (cos(a * tx) + cos(a * ty));
+    if (a == b) return 4.0 * cos(a * tx) * cos(a * ty);
+    return 4.0 * (cos(a * tx) * cos(b * ty) + cos(b * tx) * cos(a * ty));
+}
+
+static int design_one_2d(const orc_desc* d, int apply_scale, const double* A, int j,
+                         double* tab_row, double* maxgain, double* passerr, double* scale)
+{
+    const int M = (d->ntaps - 1) / 2, NU = (M + 1) * (M + 2) / 2;
+    const int L = d->ngrid, LL = L * L, Lc = d->ncheck;
+    const double dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
+    const double kappa = (d->kmin + (double)j * dk) * d->dx;
+    const double zeta = d->dz / d->dx;
+    const double edge = kappa * sin(d->theta_max_deg * PI / 180.0);
+
+    double* w = (double*)malloc((size_t)LL * sizeof(double));
+    cplx* D = (cplx*)malloc((size_t)LL * sizeof(cplx));
+    cplx* h = (cplx*)malloc((size_t)NU * sizeof(cplx));
+    if (!w || !D || !h) { free(w); free(D); free(h); return ORC_E_NOMEM; }
+    for (int i = 0; i < L; ++i) {
+        for (int q = 0; q < L; ++q) {
+            double tx = ((double)i + 0.5) * PI / (double)L;
+            double ty = ((double)q + 0.5) * PI / (double)L;
+            double r2 = tx * tx + ty * ty, k2 = kappa * kappa;
+            double rr = sqrt(r2);
+            size_t e = (size_t)i * L + q;
+            if (r2 <= k2) D[e] = cexp(I * (zeta * sqrt(k2 - r2)));
+            else D[e] = exp(-zeta * sqrt(r2 - k2));
+            if (rr <= edge) w[e] = d->w_pass;
+            else if (rr <= kappa) w[e] = d->w_trans;
+            else w[e] = d->w_evan;
+        }
+    }
+    int rc = wls_solve(A, LL, NU, w, D, d->lambda, h);
+    for (int it = 0; rc == ORC_OK && it < d->nreweight; ++it) {
+        for (int e = 0; e < LL; ++e) {
+            cplx H = 0.0;
+            for (int u = 0; u < NU; ++u) H += A[(size_t)e * NU + u] * h[u];
+            double excess = cabs(H) - 1.0;
+            if (excess > 0.0) w[e] = w[e] * (1.0 + d->beta * excess / d->tau);
+        }
+        rc = wls_solve(A, LL, NU, w, D, d->lambda, h);
+    }
+    if (rc != ORC_OK) { free(w); free(D); free(h); return rc; }
+
+    /* Response on the Lc x Lc check grid, as the double sum over the
+     * unexpanded (2M+1)^2 filter written with cosines: for each grid row the
+     * inner sum over n2 of h[n1][n2] cos(n2 ty) is formed first. */
+    double* cs = (double*)malloc((size_t)Lc * (M + 1) * sizeof(double));
+    cplx* rowsum = (cplx*)malloc((size_t)(M + 1) * sizeof(cplx));
+    if (!cs || !rowsum) { free(cs); free(rowsum); free(w); free(D); free(h); return ORC_E_NOMEM; }
+    for (int i = 0; i < Lc; ++i)
+        for (int n = 0; n <= M; ++n)
+            cs[(size_t)i * (M + 1) + n] = cos((double)n * ((double)i + 0.5) * PI / (double)Lc);
+    double g = 0.0;
+    for (int q = 0; q < Lc; ++q) {
+        const double* cy = cs + (size_t)q * (M + 1);
+        for (int n1 = 0; n1 <= M; ++n1) {  /* |n1|; both signs of n2 folded */
+            cplx acc = 0.0;
+            for (int n2 = -M; n2 <= M; ++n2) {
+                int a = n1 > abs(n2) ? n1 : abs(n2), b = n1 > abs(n2) ? abs(n2) : n1;
+                acc += h[a * (a + 1) / 2 + b] * cy[abs(n2)];
+            }
+            rowsum[n1] = acc;
+        }
+        for (int i = 0; i < Lc; ++i) {
+            const double* cx = cs + (size_t)i * (M + 1);
+            cplx H = rowsum[0];
+            for (int n1 = 1; n1 <= M; ++n1) H += 2.0 * cx[n1] * rowsum[n1];
+            double v = cabs(H);
+            if (v > g) g = v;
+        }
+    }
+    free(cs);
+    free(rowsum);
+    double s = 1.0;
+    if (apply_scale) {
+        double c = cos((double)M * PI / (2.0 * (double)Lc));
+        double lim = (1.0 - d->margin) * c * c;
+        if (g > lim) s = lim / g;
+    }
+    for (int u = 0; u < NU; ++u) h[u] = s * h[u];
+    double perr = 0.0;
+    for (int e = 0; e < LL; ++e) {
+        int i = e / L, q = e % L;
+        double tx = ((double)i + 0.5) * PI / (double)L;
+        double ty = ((double)q + 0.5) * PI / (double)L;
+        if (!(sqrt(tx * tx + ty * ty) <= edge)) continue;
+        cplx H = 0.0;
+        for (int u = 0; u < NU; ++u) H += A[(size_t)e * NU + u] * h[u];
+        double err = cabs(H - D[e]);
+        if (err > perr) perr = err;
+    }
+    for (int u = 0; u < NU; ++u) {
+        tab_row[2 * u] = creal(h[u]);
+        tab_row[2 * u + 1] = cimag(h[u]);
+    }
+    if (maxgain) *maxgain = s * g;
+    if (passerr) *passerr = perr;
+    if (scale) *scale = s;
+    free(w); free(D); free(h);
+    return ORC_OK;
+}
+
+int orc_design_table_2d(const orc_desc* d, int apply_scale, double* tab,
+                        double* maxgain, double* passerr, double* scale)
+{
+    if (!desc_ok(d) || !tab) return ORC_E_ARG;
+    const int M = (d->ntaps - 1) / 2, NU = (M + 1) * (M + 2) / 2, L = d->ngrid;
+    double* A = (double*)malloc((size_t)L * L * NU * sizeof(double));
+    if (!A) return ORC_E_NOMEM;
+    for (int i = 0; i < L; ++i)
+        for (int q = 0; q < L; ++q) {
+            double tx = ((double)i + 0.5) * PI / (double)L;
+            double ty = ((double)q + 0.5) * PI / (double)L;
+            for (int a = 0, u = 0; a <= M; ++a)
+                for (int b = 0; b <= a; ++b, ++u)
+                    A[((size_t)i * L + q) * NU + u] = basis2d(a, b, tx, ty);
+        }
+    int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < d->nk; ++j) {
+        int r = design_one_2d(d, apply_scale, A, j, tab + (size_t)j * 2 * NU,
+                              maxgain ? maxgain + j : NULL, passerr ? passerr + j : NULL,
+                              scale ? scale + j : NULL);
+        if (r != ORC_OK) {
+#pragma omp critical
+            rc = r;
+        }
+    }
+    free(A);
+    return rc;
+}
+
+/* 3-D depth step, Eq. (1) with a 2-D sum over (n1, n2), literally. */
+int orc_migrate3d(const orc_desc* d, const double* tab, const double* omega,
+                  int32_t nw, const float* vel, int32_t nx, int32_t ny, int32_t nz,
+                  const double* data, double* image)
+{
+    if (!desc_ok(d) || !tab || !omega || !vel || !data || !image || nw < 1 || nx < 1 ||
+        ny < 1 || nz < 1)
+        return ORC_E_ARG;
+    const int M = (d->ntaps - 1) / 2, NU = (M + 1) * (M + 2) / 2;
+    const double dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
+    const cplx* T = (const cplx*)tab;
+    const size_t np = (size_t)nx * ny * nw;
+    cplx* P = (cplx*)malloc(np * sizeof(cplx));
+    cplx* Q = (cplx*)malloc(np * sizeof(cplx));
+    if (!P || !Q) { free(P); free(Q); return ORC_E_NOMEM; }
+    memcpy(P, data, np * sizeof(cplx));
+    for (int k = 0; k < nz; ++k) {
+        if (k > 0) {
+            const float* vrow = vel + (size_t)(k - 1) * nx * ny;
+#pragma omp parallel for schedule(static)
+            for (int r = 0; r < nw; ++r) {
+                for (int x = 0; x < nx; ++x) {
+                    for (int y = 0; y < ny; ++y) {
+                        int j = index_of(dk, d->kmin, d->nk, omega[r], vrow[(size_t)x * ny + y]);
+                        const cplx* c = T + (size_t)j * NU;
+                        cplx acc = 0.0;
+                        for (int n1 = -M; n1 <= M; ++n1) {
+                            int xs = x - n1;
+                            if (xs < 0 || xs >= nx) continue;
+                            for (int n2 = -M; n2 <= M; ++n2) {
+                                int ys = y - n2;
+                                if (ys < 0 || ys >= ny) continue;
+                                int a = abs(n1), b = abs(n2);
+                                if (b > a) { int t = a; a = b; b = t; }
+                                acc += c[a * (a + 1) / 2 + b] * P[((size_t)xs * ny + ys) * nw + r];
+                            }
+                        }
+                        Q[((size_t)x * ny + y) * nw + r] = acc;
+                    }
+                }
+            }
+            cplx* t = P; P = Q; Q = t;
+        }
+        for (int x = 0; x < nx; ++x)
+            for (int y = 0; y < ny; ++y) {
+                double sum = 0.0;
+                for (int r = 0; r < nw; ++r) sum += creal(P[((size_t)x * ny + y) * nw + r]);
+                image[((size_t)k * nx + x) * ny + y] = sum;
+            }
+    }
+    free(P); free(Q);
+    return ORC_OK;
+}

@@ -99,6 +99,24 @@ int orc_demigrate(const orc_desc* d, const double* tab, const double* omega,
 int orc_transform_t(const float* p, int32_t nx, int32_t nt, double dt,
                     const double* omega, int32_t nw, double* out);
 
+/* ---- 3-D extension (Sec. II: the f-x method extends to 3-D with 2-D
+ * filters) --------------------------------------------------------------- */
+
+/* Circularly symmetric (2M+1) x (2M+1) extrapolators: h[n1][n2] = c(a, b) with
+ * a = max(|n1|,|n2|), b = min(|n1|,|n2|); coefficient (a, b), a >= b >= 0, is
+ * stored at u = a (a + 1) / 2 + b, NU = (M+1)(M+2)/2 per entry.  Same
+ * descriptor as the 1-D design; ngrid and ncheck are points per axis of the
+ * 2-D midpoint grids on (0, pi)^2.  tab: [nk][NU] complex. */
+int orc_design_table_2d(const orc_desc* d, int apply_scale, double* tab,
+                        double* maxgain, double* passerr, double* scale);
+
+/* 3-D migration: data [nx][ny][nw] complex, vel [nz][nx][ny] float32,
+ * image [nz][nx][ny]; row 0 = image of data; step k -> k+1 applies the 2-D
+ * filter of each output point (omega_r, vel[k][x][y]), zero outside the grid. */
+int orc_migrate3d(const orc_desc* d, const double* tab, const double* omega,
+                  int32_t nw, const float* vel, int32_t nx, int32_t ny, int32_t nz,
+                  const double* data, double* image);
+
 /* Number of OpenMP threads the oracle will use. */
 int orc_num_threads(void);
 

@@ -19,6 +19,12 @@ is not available here, so these models stand in for it:
   Ricker amplitude spectrum.
 * :func:`random_case` -- small random layered models with random complex data for
   parity sweeps.
+* :func:`config3` -- a batch of sections of uneven size (band-limited random data).
+* :func:`point_scatterer_3d`, :func:`config5` -- 3-D volumes for the extension to
+  2-D extrapolators: an analytic diffraction hyperboloid in constant velocity,
+  and a seeded layered volume (1500-4000 m/s) with an ellipsoidal body whose
+  exploding-reflector data are modelled by phase shift in the velocity profile
+  of the undisturbed layering at the centre of the volume.
 
 Velocities handed to the migration are *propagation* velocities: for zero-offset
 (exploding-reflector) data that is half the medium velocity.
@@ -291,3 +297,162 @@ def config3(seed: int = 3, nsec: int = 64, nx_range=(256, 2048), nz_range=(200, 
 def with_desc(sec: Section, **kw) -> Section:
     sec.desc = replace(sec.desc, **kw)
     return sec
+
+
+# --------------------------------------------------------------------------- #
+# 3-D volumes (extension with 2-D extrapolators).
+# --------------------------------------------------------------------------- #
+@dataclass
+class Volume:
+    """One 3-D zero-offset volume ready for migration."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dz: float
+    omega: np.ndarray          # [nw] float64
+    vel: np.ndarray            # [nz][nx][ny] float32 propagation velocity
+    data: np.ndarray           # [nx][ny][nw] complex128 surface plane
+    desc: TableDesc            # 2-D table: ntaps = 2M+1 per axis
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def nw(self) -> int:
+        return int(self.omega.size)
+
+
+def table2d_for(ntaps: int, nk: int, fmin: float, fmax: float, vmin_prop: float,
+                vmax_prop: float, dx: float, dz: float, ngrid: int = 96,
+                ncheck: int = 384, **kw) -> TableDesc:
+    """2-D table descriptor; ngrid/ncheck are points per axis of the 2-D grids."""
+    return table_for(ntaps, nk, fmin, fmax, vmin_prop, vmax_prop, dx, dz, ngrid=ngrid,
+                     ncheck=ncheck, **kw)
+
+
+def point_scatterer_3d(seed: int = 5, nx: int = 40, ny: int = 40, nz: int = 40, nw: int = 24,
+                       dx: float = 10.0, dz: float = 10.0, nt: int = 192, dt: float = 0.004,
+                       v_medium: float = 2000.0, fmin: float = 5.0, fmax: float = 30.0,
+                       f_ricker: float = 15.0, ntaps: int = 11, nk: int = 64) -> Volume:
+    """Constant medium velocity, one point scatterer at a seeded (x, y, z):
+    two-way diffraction times over the surface, a Ricker wavelet on each, and
+    a direct DFT along t (forward sign exp(-i omega t))."""
+    rng = np.random.default_rng(seed)
+    ix0 = int(rng.integers(nx // 3, 2 * nx // 3))
+    iy0 = int(rng.integers(ny // 3, 2 * ny // 3))
+    iz0 = int(rng.integers(nz // 3, 2 * nz // 3))
+    xs = np.arange(nx) * dx
+    ys = np.arange(ny) * dx
+    r = np.sqrt((xs[:, None] - ix0 * dx) ** 2 + (ys[None, :] - iy0 * dx) ** 2 + (iz0 * dz) ** 2)
+    t_d = 2.0 * r / v_medium                                           # [nx][ny]
+    t = np.arange(nt) * dt
+    p = ricker(t[None, None, :] - t_d[:, :, None], f_ricker)           # [nx][ny][nt]
+    om = omegas(nw, fmin, fmax)
+    data = p @ np.exp(-1j * np.outer(t, om))                           # [nx][ny][nw]
+    v_prop = v_medium / 2.0
+    vel = np.full((nz, nx, ny), v_prop, dtype=np.float32)
+    desc = table2d_for(ntaps, nk, fmin, fmax, v_prop, v_prop, dx, dz)
+    return Volume("point_scatterer_3d", nx, ny, nz, dx, dz, om, vel, data, desc,
+                  extra={"ix0": ix0, "iy0": iy0, "iz0": iz0, "seed": seed})
+
+
+def layered_volume(rng: np.random.Generator, nx: int, ny: int, nz: int, dx: float, dz: float,
+                   vlo: float = 1500.0, vhi: float = 3500.0, vbody: float = 4000.0,
+                   nlayer_range=(6, 11)):
+    """Medium velocity [nz][nx][ny] float64 of planar dipping layers plus one
+    ellipsoidal body, and the undisturbed layer velocity down the centre
+    column [nz] (draw order is part of the recipe)."""
+    X, Y, Z = nx * dx, ny * dx, nz * dz
+    nl = int(rng.integers(nlayer_range[0], nlayer_range[1]))
+    base = np.sort(rng.uniform(0.05, 0.95, nl)) * Z
+    dipx = np.tan(np.deg2rad(rng.uniform(-12.0, 12.0, nl)))
+    dipy = np.tan(np.deg2rad(rng.uniform(-12.0, 12.0, nl)))
+    vlay = np.sort(rng.uniform(vlo, vhi, nl + 1))
+    xs = np.arange(nx) * dx - X / 2.0
+    ys = np.arange(ny) * dx - Y / 2.0
+    zs = np.arange(nz) * dz
+    v = np.empty((nz, nx, ny))
+    for k in range(nz):
+        zif = base[:, None, None] + dipx[:, None, None] * xs[None, :, None] \
+            + dipy[:, None, None] * ys[None, None, :]                  # [nl][nx][ny]
+        v[k] = vlay[(zif <= zs[k]).sum(axis=0)]
+    centre = vlay[(base[:, None] <= zs[None, :]).sum(axis=0)]          # [nz]
+    c = np.array([rng.uniform(0.3, 0.7) * X, rng.uniform(0.3, 0.7) * Y,
+                  rng.uniform(0.35, 0.65) * Z])
+    ax = np.array([rng.uniform(0.08, 0.18) * X, rng.uniform(0.08, 0.18) * Y,
+                   rng.uniform(0.06, 0.15) * Z])
+    e = ((np.arange(nx) * dx - c[0]) / ax[0])[None, :, None] ** 2 \
+        + ((np.arange(ny) * dx - c[1]) / ax[1])[None, None, :] ** 2 \
+        + ((zs - c[2]) / ax[2])[:, None, None] ** 2
+    v = np.where(e <= 1.0, vbody, v)
+    return v, centre
+
+
+def phase_shift_model_3d(refl: np.ndarray, v_prop_z: np.ndarray, omega: np.ndarray,
+                         wavelet: np.ndarray, dx: float, dz: float,
+                         chunk: int = 16) -> np.ndarray:
+    """Exploding-reflector data by upward continuation in v(z) on the periodic
+    (kx, ky) grid of the volume: U_k = U_{k+1} exp(-i kz_k dz) + W R^_k with
+    evanescent components removed.  refl [nz][nx][ny] -> [nx][ny][nw]."""
+    nz, nx, ny = refl.shape
+    R = np.fft.fft2(refl, axes=(1, 2))                                # [nz][nx][ny]
+    kx = TWO_PI * np.fft.fftfreq(nx, d=dx)
+    ky = TWO_PI * np.fft.fftfreq(ny, d=dx)
+    kr2 = kx[:, None] ** 2 + ky[None, :] ** 2
+    out = np.zeros((nx, ny, omega.size), np.complex128)
+    for c0 in range(0, omega.size, chunk):
+        om = omega[c0:c0 + chunk]
+        W = wavelet[c0:c0 + chunk][:, None, None]
+        U = np.zeros((om.size, nx, ny), np.complex128)
+        ph, v_ph = None, None
+        for k in range(nz - 1, -1, -1):
+            if k < nz - 1:
+                if v_prop_z[k] != v_ph:
+                    kz2 = (om[:, None, None] / v_prop_z[k]) ** 2 - kr2[None]
+                    prop = kz2 > 0.0
+                    ph = np.where(prop, np.exp(-1j * np.sqrt(np.where(prop, kz2, 0.0)) * dz), 0.0)
+                    v_ph = v_prop_z[k]
+                U *= ph
+            U += W * R[k][None]
+        out[:, :, c0:c0 + chunk] = np.moveaxis(np.fft.ifft2(U, axes=(1, 2)), 0, 2)
+    return out
+
+
+def config5(seed: int = 5, nx: int = 256, ny: int = 256, nz: int = 200, nw: int = 128,
+            dx: float = 10.0, dz: float = 10.0, fmin: float = 5.0, fmax: float = 40.0,
+            f_ricker: float = 20.0, ntaps: int = 11, nk: int = 1024,
+            with_data: bool = True) -> Volume:
+    """3-D layered volume with an ellipsoidal body; 11 x 11 extrapolators."""
+    rng = np.random.default_rng(seed)
+    v, centre = layered_volume(rng, nx, ny, nz, dx, dz)
+    vel = (v / 2.0).astype(np.float32)
+    om = omegas(nw, fmin, fmax)
+    refl = np.zeros_like(v)
+    refl[:-1] = np.sign(v[1:] - v[:-1])
+    if with_data:
+        W = ricker_spectrum(om / TWO_PI, f_ricker)
+        data = phase_shift_model_3d(refl, centre / 2.0, om, W, dx, dz)
+    else:
+        data = np.zeros((nx, ny, nw), np.complex128)
+    desc = table2d_for(ntaps, nk, fmin, fmax, 750.0, 2000.0, dx, dz)
+    return Volume("config5_layers_ellipsoid", nx, ny, nz, dx, dz, om, vel, data, desc,
+                  extra={"refl": refl, "seed": seed})
+
+
+def random_volume(seed: int, nx: int, ny: int, nz: int, nw: int, ntaps: int = 11,
+                  nk: int = 64, layered: bool = True, fmin: float = 5.0,
+                  fmax: float = 40.0, dx: float = 10.0, dz: float = 10.0) -> Volume:
+    """Random velocity volume (layered or per-point random) and random complex
+    data, for parity sweeps."""
+    rng = np.random.default_rng(seed)
+    if layered:
+        v, _ = layered_volume(rng, nx, ny, nz, dx, dz, nlayer_range=(2, 6))
+    else:
+        v = rng.uniform(1500.0, 4000.0, (nz, nx, ny))
+    vel = (v / 2.0).astype(np.float32)
+    om = omegas(nw, fmin, fmax)
+    data = rng.standard_normal((nx, ny, nw)) + 1j * rng.standard_normal((nx, ny, nw))
+    desc = table2d_for(ntaps, nk, fmin, fmax, 750.0, 2000.0, dx, dz, ngrid=48, ncheck=192)
+    return Volume("random_volume_%d" % seed, nx, ny, nz, dx, dz, om, vel, data, desc,
+                  extra={"seed": seed})
