@@ -291,6 +291,69 @@ MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec,
  * rounding. */
 MIG_API int mig_kernel_kind(int32_t nx, int32_t ntaps);
 
+/*
+ * 3-D extension (Sec. II: the explicit f-x method carries over to 3-D, with
+ * 2-D extrapolators in Eq. (1)).
+ *
+ * Circularly symmetric (2M+1) x (2M+1) filters: h[n1][n2] = c(a, b) with
+ * a = max(|n1|,|n2|), b = min(|n1|,|n2|).  A 2-D table holds the unique
+ * coefficients of each entry, u = a (a + 1) / 2 + b for 0 <= b <= a <= M,
+ * NU = (M+1)(M+2)/2 complex values per entry: tab [nk][NU].
+ *
+ * Design (same descriptor; ngrid and ncheck count points per axis of the
+ * midpoint grids on (0, pi)^2): per entry, the weighted least-squares fit of
+ * sum_u c_u B_u(tx, ty) to the phase shift exp(+i zeta sqrt(kappa^2 - r^2))
+ * (r^2 = tx^2 + ty^2; exp(-zeta sqrt(r^2 - kappa^2)) past kappa), with the
+ * 1-D band weights and reweighting applied at radius r, where B_u is the sum
+ * of cos(n1 tx) cos(n2 ty) over the taps of coefficient u.  The stability
+ * scale applies the 1-D Bernstein bound along each axis:
+ *   |H|max <= max over the Lc x Lc check grid / cos(M pi / (2 Lc))^2,
+ * and scales the entry to (1 - margin) cos(M pi / (2 Lc))^2 when that is
+ * exceeded.  Returns as mig_design_table (synchronizes the stream).
+ */
+#define MIG_MAX_NTAPS_2D 11     /* 2M+1 per axis, M <= 5 (NU <= 21)           */
+#define MIG_MAX_NGRID_2D 64     /* design grid points per axis                */
+#define MIG_MAX_NCHECK_2D 4096  /* check grid points per axis                 */
+#define MIG_MAX_NXY 65536       /* lateral points per axis of a volume        */
+
+MIG_API size_t mig_design2d_workspace_size(const mig_table_desc* d);
+MIG_API int mig_design_table_2d(const mig_table_desc* d, mig_c128* tab64,
+                                mig_c64* tab32, double* maxgain,
+                                double* passerr, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/*
+ * 3-D migration: Algorithm 1 on a volume.
+ *   data  [nw][nx][ny] complex surface wavefield (one contiguous plane per
+ *         frequency)
+ *   vel   [nz][nx][ny] propagation velocity; step k-1 -> k uses vel[k-1]
+ *         (last slice unused); v <= 0 or NaN selects entry 0
+ *   image [nz][nx][ny] FP64 output; slice 0 = sum over omega of Re data,
+ *         slice k = sum over omega of Re P_k
+ *   plane_out  optional [nw][nx][ny] copy of the last wavefield P_{nz-1}
+ *         (NULL = not wanted; for nz = 1 it is the data)
+ * One step: P_k(x, y) = sum over |n1|,|n2| <= M of h_j[n1][n2]
+ *   P_{k-1}(x - n1, y - n2), with P zero outside the volume and j the
+ *   nearest entry for omega / vel[k-1][x][y] (the mig_table_index rule).
+ * The image sums Re over frequencies in FP64: within groups of
+ * omegas_per_group consecutive frequencies in order, then over groups in
+ * order (0 = library choice, see mig_omegas_per_group_3d); results are
+ * deterministic for a given grouping.  ntaps <= MIG_MAX_NTAPS_2D.
+ * ws >= mig_migrate3d_workspace_size(...) bytes of device memory, disjoint
+ * from data, image and plane_out.  Asynchronous on `stream`.
+ */
+MIG_API int mig_omegas_per_group_3d(int32_t nx, int32_t ny, int32_t nw,
+                                    int32_t want);
+MIG_API size_t mig_migrate3d_workspace_size(int32_t nx, int32_t ny, int32_t nw,
+                                            int32_t nz,
+                                            int32_t omegas_per_group);
+MIG_API int mig_migrate3d(const mig_c64* data, const float* vel,
+                          const double* omega, const mig_c64* tab32,
+                          const mig_table_desc* d, int32_t nx, int32_t ny,
+                          int32_t nw, int32_t nz, int32_t omegas_per_group,
+                          double* image, mig_c64* plane_out, void* ws,
+                          size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

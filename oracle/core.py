@@ -99,7 +99,7 @@ def load():
     lib.orc_num_threads.argtypes = []
     lib.orc_transform_t.argtypes = [P, i32, i32, C.c_double, P, i32, P]
     lib.orc_design_table_2d.argtypes = [D, C.c_int, P, P, P, P]
-    lib.orc_migrate3d.argtypes = [D, P, P, i32, P, i32, i32, i32, P, P]
+    lib.orc_migrate3d.argtypes = [D, P, P, i32, P, i32, i32, i32, P, P, P]
     for f in ("orc_design_table", "orc_table_index", "orc_extrapolate",
               "orc_image", "orc_migrate", "orc_demigrate", "orc_num_threads",
               "orc_transform_t", "orc_design_table_2d", "orc_migrate3d"):
@@ -248,8 +248,9 @@ def design_table_2d(desc, apply_scale: bool = True):
     return tab, mg, pe, sc
 
 
-def migrate3d(desc, tab, omega, vel, data):
-    """data [nx][ny][nw] complex, vel [nz][nx][ny] -> image [nz][nx][ny]."""
+def migrate3d(desc, tab, omega, vel, data, want_plane=False):
+    """data [nx][ny][nw] complex, vel [nz][nx][ny] -> image [nz][nx][ny]
+    (and the last plane [nx][ny][nw] when want_plane)."""
     d = OrcDesc.from_obj(desc) if not isinstance(desc, OrcDesc) else desc
     tab = _c128(tab)
     omega = _f64(omega)
@@ -259,7 +260,8 @@ def migrate3d(desc, tab, omega, vel, data):
     nz = vel.shape[0]
     assert vel.shape == (nz, nx, ny) and omega.size == nw
     img = np.zeros((nz, nx, ny))
+    last = np.zeros_like(data) if want_plane else None
     cd = d.c()
     _check(load().orc_migrate3d(C.byref(cd), _ptr(tab), _ptr(omega), nw, _ptr(vel), nx, ny, nz,
-                                _ptr(data), _ptr(img)), "migrate3d")
-    return img
+                                _ptr(data), _ptr(img), _ptr(last)), "migrate3d")
+    return (img, last) if want_plane else img

@@ -567,7 +567,7 @@ int orc_design_table_2d(const orc_desc* d, int apply_scale, double* tab,
 /* 3-D depth step, Eq. (1) with a 2-D sum over (n1, n2), literally. */
 int orc_migrate3d(const orc_desc* d, const double* tab, const double* omega,
                   int32_t nw, const float* vel, int32_t nx, int32_t ny, int32_t nz,
-                  const double* data, double* image)
+                  const double* data, double* image, double* plane_out)
 {
     if (!desc_ok(d) || !tab || !omega || !vel || !data || !image || nw < 1 || nx < 1 ||
         ny < 1 || nz < 1)
@@ -614,6 +614,7 @@ int orc_migrate3d(const orc_desc* d, const double* tab, const double* omega,
                 image[((size_t)k * nx + x) * ny + y] = sum;
             }
     }
+    if (plane_out) memcpy(plane_out, P, np * sizeof(cplx));
     free(P); free(Q);
     return ORC_OK;
 }

@@ -112,10 +112,11 @@ int orc_design_table_2d(const orc_desc* d, int apply_scale, double* tab,
 
 /* 3-D migration: data [nx][ny][nw] complex, vel [nz][nx][ny] float32,
  * image [nz][nx][ny]; row 0 = image of data; step k -> k+1 applies the 2-D
- * filter of each output point (omega_r, vel[k][x][y]), zero outside the grid. */
+ * filter of each output point (omega_r, vel[k][x][y]), zero outside the grid.
+ * plane_out ([nx][ny][nw] complex) or NULL receives the last wavefield. */
 int orc_migrate3d(const orc_desc* d, const double* tab, const double* omega,
                   int32_t nw, const float* vel, int32_t nx, int32_t ny, int32_t nz,
-                  const double* data, double* image);
+                  const double* data, double* image, double* plane_out);
 
 /* Number of OpenMP threads the oracle will use. */
 int orc_num_threads(void);

@@ -582,3 +582,162 @@ MIG_API int mig_kernel_kind(int32_t nx, int32_t ntaps)
 }
 
 }  // extern "C"
+
+// ---- 3-D extension ------------------------------------------------------ //
+
+namespace {
+
+bool design2d_desc_valid(const mig_table_desc* d)
+{
+    return design_desc_valid(d) && d->ntaps <= MIG_MAX_NTAPS_2D &&
+           d->ngrid <= MIG_MAX_NGRID_2D && d->ncheck <= MIG_MAX_NCHECK_2D;
+}
+
+bool sizes3d_ok(int32_t nx, int32_t ny, int32_t nw, int32_t nz)
+{
+    return nx >= 1 && nx <= MIG_MAX_NXY && ny >= 1 && ny <= MIG_MAX_NXY && nw >= 1 &&
+           nw <= MIG_MAX_NW && nz >= 1;
+}
+
+// Frequencies per workgroup group: `want` if given, else enough groups that
+// the grid holds two workgroups per CU.
+int omegas_per_group3d(int32_t nx, int32_t ny, int32_t nw, int32_t want)
+{
+    if (want > 0) return want < nw ? want : nw;
+    const int tiles = step3d_tiles_x(nx) * step3d_tiles_y(ny);
+    int groups = (2 * device_cus() + tiles - 1) / tiles;
+    if (groups < 1) groups = 1;
+    int wpg = (nw + groups - 1) / groups;
+    return wpg < 1 ? 1 : wpg;
+}
+
+size_t plane3d_bytes(int32_t nx, int32_t ny, int32_t nw)
+{
+    return align_up((size_t)nx * ny * nw * sizeof(float2), kAlign);
+}
+
+size_t partial3d_bytes(int32_t nx, int32_t ny, int ngroups)
+{
+    return align_up((size_t)ngroups * nx * ny * sizeof(double), kAlign);
+}
+
+}  // namespace
+
+MIG_API size_t mig_design2d_workspace_size(const mig_table_desc* d)
+{
+    if (!design2d_desc_valid(d)) return 0;
+    const size_t M = (size_t)(d->ntaps - 1) / 2, NU = (M + 1) * (M + 2) / 2;
+    return align_up((size_t)d->ngrid * d->ngrid * NU * sizeof(double), kAlign) +
+           align_up((size_t)d->ncheck * (M + 1) * sizeof(double), kAlign) +
+           align_up((size_t)d->nk * sizeof(int), kAlign);
+}
+
+MIG_API int mig_design_table_2d(const mig_table_desc* d, mig_c128* tab64, mig_c64* tab32,
+                                double* maxgain, double* passerr, void* ws, size_t ws_bytes,
+                                void* stream)
+{
+    if (!design2d_desc_valid(d) || !tab64) return MIG_E_ARG;
+    const size_t need = mig_design2d_workspace_size(d);
+    if (!ws || ws_bytes < need) return MIG_E_WORKSPACE;
+    const size_t M = (size_t)(d->ntaps - 1) / 2, NU = (M + 1) * (M + 2) / 2;
+    if (tab32 && overlap(tab64, d->nk * NU * sizeof(mig_c128), tab32, d->nk * NU * sizeof(mig_c64)))
+        return MIG_E_ARG;
+    hipStream_t s = as_stream(stream);
+    char* p = static_cast<char*>(ws);
+    double* A = reinterpret_cast<double*>(p);
+    p += align_up((size_t)d->ngrid * d->ngrid * NU * sizeof(double), kAlign);
+    double* CS = reinterpret_cast<double*>(p);
+    p += align_up((size_t)d->ncheck * (M + 1) * sizeof(double), kAlign);
+    int* status = reinterpret_cast<int*>(p);
+
+    int rc = launch_design2d_basis(d, A, CS, s);
+    if (rc == MIG_OK) rc = launch_design2d(d, A, CS, tab64, tab32, maxgain, passerr, status, s);
+    if (rc != MIG_OK) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return MIG_E_DEVICE;
+    std::vector<int> st((size_t)d->nk);
+    if (hipMemcpy(st.data(), status, st.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return MIG_E_DEVICE;
+    int worst = 0;
+    for (int v : st) worst = v > worst ? v : worst;
+    if (worst == 2) return MIG_E_ARG;
+    if (worst == 1) return MIG_E_UNSTABLE;
+    return MIG_OK;
+}
+
+MIG_API int mig_omegas_per_group_3d(int32_t nx, int32_t ny, int32_t nw, int32_t want)
+{
+    if (!sizes3d_ok(nx, ny, nw, 1) || want < 0) return -1;
+    return omegas_per_group3d(nx, ny, nw, want);
+}
+
+MIG_API size_t mig_migrate3d_workspace_size(int32_t nx, int32_t ny, int32_t nw, int32_t nz,
+                                            int32_t omegas_per_group)
+{
+    if (!sizes3d_ok(nx, ny, nw, nz) || omegas_per_group < 0) return 0;
+    const int wpg = omegas_per_group3d(nx, ny, nw, omegas_per_group);
+    const int ngroups = (nw + wpg - 1) / wpg;
+    return 2 * plane3d_bytes(nx, ny, nw) + 2 * partial3d_bytes(nx, ny, ngroups);
+}
+
+MIG_API int mig_migrate3d(const mig_c64* data, const float* vel, const double* omega,
+                          const mig_c64* tab32, const mig_table_desc* d, int32_t nx, int32_t ny,
+                          int32_t nw, int32_t nz, int32_t omegas_per_group, double* image,
+                          mig_c64* plane_out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!desc_valid(d) || d->ntaps > MIG_MAX_NTAPS_2D || !data || !vel || !omega || !tab32 ||
+        !image || !sizes3d_ok(nx, ny, nw, nz) || omegas_per_group < 0)
+        return MIG_E_ARG;
+    const size_t need = mig_migrate3d_workspace_size(nx, ny, nw, nz, omegas_per_group);
+    if (!ws || ws_bytes < need) return MIG_E_WORKSPACE;
+    const size_t plane = (size_t)nx * ny;
+    const size_t pb = plane * nw * sizeof(mig_c64);
+    if (overlap(ws, ws_bytes, data, pb) || overlap(ws, ws_bytes, image, plane * nz * sizeof(double)) ||
+        (plane_out && (overlap(ws, ws_bytes, plane_out, pb) || overlap(data, pb, plane_out, pb))))
+        return MIG_E_ARG;
+    hipStream_t s = as_stream(stream);
+    const int wpg = omegas_per_group3d(nx, ny, nw, omegas_per_group);
+    const int ngroups = (nw + wpg - 1) / wpg;
+    char* base = static_cast<char*>(ws);
+    float2* buf[2] = {reinterpret_cast<float2*>(base),
+                      reinterpret_cast<float2*>(base + plane3d_bytes(nx, ny, nw))};
+    double* part[2] = {
+        reinterpret_cast<double*>(base + 2 * plane3d_bytes(nx, ny, nw)),
+        reinterpret_cast<double*>(base + 2 * plane3d_bytes(nx, ny, nw) +
+                                  partial3d_bytes(nx, ny, ngroups))};
+
+    const float2* src = reinterpret_cast<const float2*>(data);
+    int rc = launch_image3d(src, image, plane, nw, s);
+    if (rc != MIG_OK) return rc;
+    Step3dArgs a;
+    a.tab = reinterpret_cast<const float2*>(tab32);
+    a.omega = omega;
+    a.nx = nx;
+    a.ny = ny;
+    a.nw = nw;
+    a.nk = d->nk;
+    a.wpg = wpg;
+    a.ngroups = ngroups;
+    a.tiles_x = step3d_tiles_x(nx);
+    a.tiles_y = step3d_tiles_y(ny);
+    a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
+    a.b = d->kmin / a.dk;
+    const int M = (d->ntaps - 1) / 2;
+    for (int k = 1; k < nz; ++k) {
+        a.in = src;
+        a.out = buf[k & 1];
+        a.vel = vel + (size_t)(k - 1) * plane;
+        a.part = part[k & 1];
+        a.prev = k >= 2 ? part[(k - 1) & 1] : nullptr;
+        a.prev_row = k >= 2 ? image + (size_t)(k - 1) * plane : nullptr;
+        rc = launch_step3d(a, M, s);
+        if (rc != MIG_OK) return rc;
+        src = a.out;
+    }
+    if (nz >= 2) {
+        rc = launch_reduce3d(part[(nz - 1) & 1], image + (size_t)(nz - 1) * plane, plane, ngroups, s);
+        if (rc != MIG_OK) return rc;
+    }
+    if (plane_out && hipMemcpyAsync(plane_out, src, pb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MIG_E_DEVICE;
+    return MIG_OK;
+}

@@ -152,6 +152,31 @@ int launch_transform(const float* section, int nx, int nt, double dt, const doub
                      int nw, float2* out, float* B, hipStream_t s);
 int launch_image(const float2* wf, double* row, int nx, int nw, hipStream_t s);
 
+// One 3-D depth step (device pointers; planes are [nw][nx][ny]).
+struct Step3dArgs {
+    const float2* in;       // plane before the step
+    float2* out;            // plane after the step
+    const float* vel;       // [nx][ny] velocity of this step
+    const float2* tab;      // [nk][NU] 2-D table
+    const double* omega;    // [nw]
+    double* part;           // [ngroups][nx][ny] partial image of the new plane
+    const double* prev;     // partials of the previous step, or nullptr
+    double* prev_row;       // image row receiving the previous step's sum
+    int nx, ny, nw, nk;
+    int wpg, ngroups;       // frequencies per group, groups
+    int tiles_x, tiles_y;
+    double dk, b;           // table spacing, kmin / dk
+};
+int step3d_tiles_x(int nx);
+int step3d_tiles_y(int ny);
+int launch_step3d(const Step3dArgs& a, int M, hipStream_t s);
+int launch_image3d(const float2* wf, double* row, size_t plane, int nw, hipStream_t s);
+int launch_reduce3d(const double* part, double* row, size_t plane, int ngroups, hipStream_t s);
+int launch_design2d_basis(const mig_table_desc* d, double* A, double* CS, hipStream_t s);
+int launch_design2d(const mig_table_desc* d, const double* A, const double* CS,
+                    mig_c128* tab64, mig_c64* tab32, double* maxgain, double* passerr,
+                    int* status, hipStream_t s);
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace mig

@@ -130,10 +130,34 @@ __device__ double block_max(double v, DesignShared& sh)
 }
 
 struct DesignParams {
-    int nk, K, L, Lc, nreweight;
+    int nk, K, L, Lc, nreweight, M;
     double kmin, dk, dx, zeta, edge_sin;
     double w_pass, w_trans, w_evan, lambda, beta, tau, margin;
 };
+
+DesignParams design_params(const mig_table_desc* d)
+{
+    DesignParams P;
+    P.nk = d->nk;
+    P.K = 0;
+    P.M = (d->ntaps - 1) / 2;
+    P.L = d->ngrid;
+    P.Lc = d->ncheck;
+    P.nreweight = d->nreweight;
+    P.kmin = d->kmin;
+    P.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
+    P.dx = d->dx;
+    P.zeta = d->dz / d->dx;
+    P.edge_sin = sin(d->theta_max_deg * kPi / 180.0);
+    P.w_pass = d->w_pass;
+    P.w_trans = d->w_trans;
+    P.w_evan = d->w_evan;
+    P.lambda = d->lambda;
+    P.beta = d->beta;
+    P.tau = d->tau;
+    P.margin = d->margin;
+    return P;
+}
 
 __global__ void __launch_bounds__(kDesignThreads)
 k_design(DesignParams P, const double* __restrict__ A, const double* __restrict__ C,
@@ -217,7 +241,165 @@ k_design(DesignParams P, const double* __restrict__ A, const double* __restrict_
     }
 }
 
+// ---- 2-D circularly symmetric extrapolators (3-D extension, Sec. II) ----
+//
+// Unique coefficient u = a (a + 1) / 2 + b, a >= b >= 0, stands for the taps
+// (n1, n2) with max(|n1|,|n2|) = a and min = b.  Its basis function on
+// (theta_x, theta_y) is the sum of cos(n1 tx) cos(n2 ty) over that orbit:
+//   1;  2 (cos a tx + cos a ty);  4 cos a tx cos a ty;
+//   4 (cos a tx cos b ty + cos b tx cos a ty)          (a = 0; b = 0; a = b; a > b).
+__device__ __forceinline__ double orbit_basis(int a, int b, const double* cx, const double* cy)
+{
+#pragma clang fp contract(off)
+    if (a == 0) return 1.0;
+    if (b == 0) return 2.0 * (cx[a] + cy[a]);
+    if (a == b) return 4.0 * cx[a] * cy[a];
+    return 4.0 * (cx[a] * cy[b] + cx[b] * cy[a]);
+}
+
+// A[(i L + q)][u] on the L x L design midpoint grid; CS[c][n] = cos(n theta_c)
+// on the Lc check grid (the check evaluates the basis from it).
+__global__ void k_design2d_basis(int L, int Lc, int M, double* A, double* CS)
+{
+#pragma clang fp contract(off)
+    const int NU = (M + 1) * (M + 2) / 2;
+    const size_t nA = (size_t)L * L, total = nA + (size_t)Lc;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        if (e < nA) {
+            const int i = (int)(e / L), q = (int)(e % L);
+            double cx[kMaxK], cy[kMaxK];
+            const double tx = ((double)i + 0.5) * kPi / (double)L;
+            const double ty = ((double)q + 0.5) * kPi / (double)L;
+            for (int n = 0; n <= M; ++n) { cx[n] = cos((double)n * tx); cy[n] = cos((double)n * ty); }
+            for (int a = 0, u = 0; a <= M; ++a)
+                for (int b = 0; b <= a; ++b, ++u) A[e * NU + u] = orbit_basis(a, b, cx, cy);
+        } else {
+            const int c = (int)(e - nA);
+            const double th = ((double)c + 0.5) * kPi / (double)Lc;
+            for (int n = 0; n <= M; ++n) CS[(size_t)c * (M + 1) + n] = cos((double)n * th);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kDesignThreads)
+k_design2d(DesignParams P, const double* __restrict__ A, const double* __restrict__ CS,
+           mig_c128* tab64, mig_c64* tab32, double* maxgain, double* passerr, int* status)
+{
+#pragma clang fp contract(off)
+    extern __shared__ double dyn[];
+    __shared__ DesignShared sh;
+    const int j = blockIdx.x, NU = P.K, L = P.L, Lc = P.Lc, LL = L * L;
+    const int M = P.M;
+    double* w = dyn;
+    double* Dr = dyn + LL;
+    double* Di = dyn + 2 * LL;
+
+    const double kappa = (P.kmin + (double)j * P.dk) * P.dx;
+    const double k2 = kappa * kappa;
+    const double edge = kappa * P.edge_sin;
+    if (threadIdx.x == 0) sh.fail = 0;
+    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+        const double tx = ((double)(e / L) + 0.5) * kPi / (double)L;
+        const double ty = ((double)(e % L) + 0.5) * kPi / (double)L;
+        const double r2 = tx * tx + ty * ty;
+        const double r = sqrt(r2);
+        if (r2 <= k2) {
+            double sn, cs;
+            sincos(P.zeta * sqrt(k2 - r2), &sn, &cs);
+            Dr[e] = cs;
+            Di[e] = sn;
+        } else {
+            Dr[e] = exp(-P.zeta * sqrt(r2 - k2));
+            Di[e] = 0.0;
+        }
+        w[e] = r <= edge ? P.w_pass : (r <= kappa ? P.w_trans : P.w_evan);
+    }
+    __syncthreads();
+
+    wls_solve(A, w, Dr, Di, LL, NU, P.lambda, sh);
+    for (int it = 0; it < P.nreweight; ++it) {
+        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+            double Hr = 0.0, Hi = 0.0;
+            const double* a = A + (size_t)e * NU;
+            for (int u = 0; u < NU; ++u) { Hr += a[u] * sh.hr[u]; Hi += a[u] * sh.hi[u]; }
+            const double excess = hypot(Hr, Hi) - 1.0;
+            if (excess > 0.0) w[e] = w[e] * (1.0 + P.beta * excess / P.tau);
+        }
+        __syncthreads();
+        wls_solve(A, w, Dr, Di, LL, NU, P.lambda, sh);
+    }
+
+    // Stability scale: the per-axis Bernstein bound applied twice,
+    // |H|max <= max_grid |H| / cos(M pi / (2 Lc))^2.
+    double g = 0.0;
+    for (int e = threadIdx.x; e < Lc * Lc; e += blockDim.x) {
+        const double* cx = CS + (size_t)(e / Lc) * (M + 1);
+        const double* cy = CS + (size_t)(e % Lc) * (M + 1);
+        double Hr = 0.0, Hi = 0.0;
+        for (int a = 0, u = 0; a <= M; ++a)
+            for (int b = 0; b <= a; ++b, ++u) {
+                const double f = orbit_basis(a, b, cx, cy);
+                Hr += f * sh.hr[u];
+                Hi += f * sh.hi[u];
+            }
+        g = fmax(g, hypot(Hr, Hi));
+    }
+    g = block_max(g, sh);
+    const double c = cos((double)M * kPi / (2.0 * (double)Lc));
+    const double lim = (1.0 - P.margin) * c * c;
+    const double s = g > lim ? lim / g : 1.0;
+
+    double perr = 0.0;
+    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+        const double tx = ((double)(e / L) + 0.5) * kPi / (double)L;
+        const double ty = ((double)(e % L) + 0.5) * kPi / (double)L;
+        if (!(sqrt(tx * tx + ty * ty) <= edge)) continue;
+        const double* a = A + (size_t)e * NU;
+        double Hr = 0.0, Hi = 0.0;
+        for (int u = 0; u < NU; ++u) { Hr += a[u] * (s * sh.hr[u]); Hi += a[u] * (s * sh.hi[u]); }
+        perr = fmax(perr, hypot(Hr - Dr[e], Hi - Di[e]));
+    }
+    perr = block_max(perr, sh);
+
+    for (int u = threadIdx.x; u < NU; u += blockDim.x) {
+        const double hr = s * sh.hr[u], hi = s * sh.hi[u];
+        tab64[(size_t)j * NU + u] = mig_c128{hr, hi};
+        if (tab32) tab32[(size_t)j * NU + u] = mig_c64{(float)hr, (float)hi};
+    }
+    if (threadIdx.x == 0) {
+        const double mg = s * g;
+        if (maxgain) maxgain[j] = mg;
+        if (passerr) passerr[j] = perr;
+        status[j] = sh.fail ? 2 : (mg <= 1.0 ? 0 : 1);
+    }
+}
+
 }  // namespace
+
+int launch_design2d_basis(const mig_table_desc* d, double* A, double* CS, hipStream_t s)
+{
+    const int M = (d->ntaps - 1) / 2;
+    const size_t total = (size_t)d->ngrid * d->ngrid + d->ncheck;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_design2d_basis, dim3((unsigned)blocks), dim3(256), 0, s, d->ngrid,
+                       d->ncheck, M, A, CS);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+int launch_design2d(const mig_table_desc* d, const double* A, const double* CS,
+                    mig_c128* tab64, mig_c64* tab32, double* maxgain, double* passerr,
+                    int* status, hipStream_t s)
+{
+    DesignParams P = design_params(d);
+    P.M = (d->ntaps - 1) / 2;
+    P.K = (P.M + 1) * (P.M + 2) / 2;
+    const size_t lds = (size_t)3 * d->ngrid * d->ngrid * sizeof(double);
+    hipLaunchKernelGGL(k_design2d, dim3(d->nk), dim3(kDesignThreads), lds, s, P, A, CS, tab64,
+                       tab32, maxgain, passerr, status);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
 
 int launch_design_basis(const mig_table_desc* d, double* A, double* C, hipStream_t s)
 {
@@ -234,24 +416,8 @@ int launch_design(const mig_table_desc* d, const double* A, const double* C,
                   mig_c128* tab64, mig_c64* tab32, double* maxgain,
                   double* passerr, int* status, hipStream_t s)
 {
-    DesignParams P;
-    P.nk = d->nk;
+    DesignParams P = design_params(d);
     P.K = (d->ntaps - 1) / 2 + 1;
-    P.L = d->ngrid;
-    P.Lc = d->ncheck;
-    P.nreweight = d->nreweight;
-    P.kmin = d->kmin;
-    P.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);
-    P.dx = d->dx;
-    P.zeta = d->dz / d->dx;
-    P.edge_sin = sin(d->theta_max_deg * kPi / 180.0);
-    P.w_pass = d->w_pass;
-    P.w_trans = d->w_trans;
-    P.w_evan = d->w_evan;
-    P.lambda = d->lambda;
-    P.beta = d->beta;
-    P.tau = d->tau;
-    P.margin = d->margin;
     size_t lds = (size_t)3 * d->ngrid * sizeof(double);
     hipLaunchKernelGGL(k_design, dim3(d->nk), dim3(kDesignThreads), lds, s, P, A, C,
                        tab64, tab32, maxgain, passerr, status);

@@ -1,0 +1,390 @@
+// 3-D extension (Sec. II): the depth step of Eq. (1) with circularly
+// symmetric (2M+1) x (2M+1) extrapolators, and the image of each new plane
+// (real part summed over frequencies, Algorithm 1) accumulated in FP64.
+//
+// Filter of output (x, y) at frequency omega: h[n1][n2] = c(a, b) with
+// a = max(|n1|,|n2|), b = min; the unique coefficients (a >= b >= 0) are stored
+// at u = a (a + 1) / 2 + b.  Folding the symmetric taps, one output is
+//   out = sum_u c_u S_u,   S_u = sum of P(x + n1, y + n2) over the orbit of u,
+// formed from pair sums along y, Y_b(x') = P(x', y + b) + P(x', y - b):
+//   S(0,0) = Y_0(x)
+//   S(a,0) = Y_a(x) + Y_0(x + a) + Y_0(x - a)
+//   S(a,a) = Y_a(x + a) + Y_a(x - a)
+//   S(a,b) = Y_b(x + a) + Y_b(x - a) + Y_a(x + b) + Y_a(x - b)     (a > b > 0)
+// i.e. M + 3M + 3M(M-1)/2 complex additions (50 for M = 5) and (M+1)(M+2)/2
+// complex multiply-adds (21) per output instead of (2M+1)^2 (121).
+//
+// Layout: wavefield planes [nw][nx][ny] complex64 (y fastest), so one
+// frequency's plane is a contiguous 2-D array.
+//
+// Mapping: a workgroup owns a tile of 32 x-rows by 64 y-columns and a group of
+// consecutive frequencies.  For each frequency it stages the tile and its halo
+// of M points in LDS (one coalesced row per wave load), then each of its four
+// waves walks 8 x-rows with one y-column per lane, keeping the pair sums of the
+// 2M + 1 rows around the current output in registers (one new LDS row of
+// 2M + 1 values per output).  Taps stay in registers and are reloaded only when
+// the table entry of some lane changes.  The tile's slowness lives in LDS.
+//
+// Image: each workgroup sums Re over its frequencies in FP64 (frequency order)
+// and writes a partial row for its group; the kernel of the next depth step
+// adds the groups' partials in group order (so no atomics and no waiting), and
+// a last small kernel closes the final step.  Results are deterministic for a
+// given frequency grouping.
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace mig {
+namespace {
+
+constexpr int kLanes3 = 64;                  // y columns per tile (one per lane)
+constexpr int kWaves3 = 4;                   // waves per workgroup
+constexpr int kRows3 = 8;                    // x rows walked by each wave
+constexpr int kTileX3 = kWaves3 * kRows3;    // x rows per tile
+constexpr int kThreads3 = kWaves3 * 64;
+
+// Buffer resource word 3 for raw (unformatted, unswizzled) buffers on the
+// gfx9 family; loads beyond num_records return zero.
+constexpr int kRawBufferWord3 = 0x00020000;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 buf_load_c64(__amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
+__device__ __forceinline__ void buf_store_c64(__amdgpu_buffer_rsrc_t r, int byte_off, float2 v)
+{
+    const u32x2 u = {__float_as_uint(v.x), __float_as_uint(v.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, byte_off, 0, 0);
+}
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b)
+{
+    return make_float2(a.x + b.x, a.y + b.y);
+}
+
+__device__ __forceinline__ float2 c_mul(float2 h, float2 u)
+{
+    return make_float2(fmaf(-h.y, u.y, h.x * u.x), fmaf(h.y, u.x, h.x * u.y));
+}
+
+__device__ __forceinline__ float2 c_fma(float2 h, float2 s, float2 acc)
+{
+    acc.x = fmaf(h.x, s.x, acc.x);
+    acc.x = fmaf(-h.y, s.y, acc.x);
+    acc.y = fmaf(h.x, s.y, acc.y);
+    acc.y = fmaf(h.y, s.x, acc.y);
+    return acc;
+}
+
+// Workgroup index -> (frequency group, tile).  Consecutive workgroup indices
+// are dealt round-robin to the 8 XCDs; when the grid is a multiple of 8 the
+// index is remapped so that each XCD receives a contiguous run of tiles of
+// the same frequencies, whose halos then meet in that XCD's L2.
+__device__ __forceinline__ int logical_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
+// Coefficient index of the orbit (a, b), a >= b.
+constexpr int cidx(int a, int b) { return a * (a + 1) / 2 + b; }
+constexpr bool in_set(int p, int lo, int hi) { return p >= lo && p < hi; }
+
+// Position of orbit (a, b) among the coefficients a pass over planes [lo, hi)
+// multiplies (the orbits with a part in one of those planes), in (a, b) order.
+constexpr int pass_slot(int M, int lo, int hi, int a0, int b0)
+{
+    int n = 0;
+    for (int a = 0; a <= M; ++a)
+        for (int b = 0; b <= a; ++b) {
+            if (a == a0 && b == b0) return n;
+            if (in_set(a, lo, hi) || in_set(b, lo, hi)) ++n;
+        }
+    return n;
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// One pass of a wave over its kRows3 output rows using only the pair-sum
+// planes b in [LO, HI).  out = sum over orbits (a, b) of c(a,b) S(a,b) is
+// linear in the planes, so every orbit sum splits into a plane-a part and a
+// plane-b part:
+//   (0,0): Y_0(x)                      plane 0
+//   (a,0): Y_a(x)  | Y_0(x+a)+Y_0(x-a) planes a | 0
+//   (a,a): Y_a(x+a)+Y_a(x-a)           plane a
+//   (a,b): Y_a(x+b)+Y_a(x-b) | Y_b(x+a)+Y_b(x-a)   planes a | b
+// A pass adds the parts whose plane it holds (both parts under one
+// multiply when both planes are in the pass).  Two passes over halves of the
+// planes hold half the pair-sum window in registers, at the price of one
+// extra multiply-add for each orbit whose planes fall in different halves.
+// The last pass also finishes each output at once: Re into the image
+// partial, and a buffer store whose offset is pushed out of range for
+// points outside the volume (so no output waits behind a branch).
+template <int M, int LO, int HI, bool LAST>
+__device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const double* __restrict__ S,
+                                         int lane, int r0, double ar, const Step3dArgs& A,
+                                         __amdgpu_buffer_rsrc_t rt, float2 (&acc)[kRows3],
+                                         double (&img)[kRows3], __amdgpu_buffer_rsrc_t rq,
+                                         int qbase, int ny8)
+{
+    constexpr int W = kLanes3 + 2 * M;
+    constexpr int NP = HI - LO;
+    constexpr int NR = kRows3 + 2 * M;
+    constexpr int NC = pass_slot(M, LO, HI, M + 1, 0);
+    constexpr int NU = (M + 1) * (M + 2) / 2;
+    float2 h[NC];
+    int jcur = -1;
+    float2 Y[NR][NP];
+    static_for<0, NR>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const float2* row = Tw + i * W;
+        static_for<0, NP>([&](auto Q) {
+            constexpr int b = LO + decltype(Q)::value;
+            if constexpr (b == 0) {
+                Y[i][0] = row[0];
+            } else {
+                Y[i][b - LO] = c_add(row[b], row[-b]);
+                // Keep the pair sum (not its two operands) alive across rows.
+                __asm__ volatile("" : "+v"(Y[i][b - LO].x), "+v"(Y[i][b - LO].y));
+            }
+        });
+        if constexpr (i >= 2 * M) {
+            constexpr int r = i - 2 * M;  // output row x0 + r0 + r
+            constexpr int c = r + M;      // its pair sums
+            const int j = index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
+            if (__builtin_amdgcn_ballot_w64(j != jcur) != 0) {
+                const int toff = j * (NU * 8);
+                static_for<0, M + 1>([&](auto AA) {
+                    constexpr int a = decltype(AA)::value;
+                    static_for<0, a + 1>([&](auto BB) {
+                        constexpr int b = decltype(BB)::value;
+                        if constexpr (in_set(a, LO, HI) || in_set(b, LO, HI))
+                            h[pass_slot(M, LO, HI, a, b)] = buf_load_c64(rt, toff + cidx(a, b) * 8);
+                    });
+                });
+                jcur = j;
+            }
+            float2 o = acc[r];
+            static_for<0, M + 1>([&](auto AA) {
+                constexpr int a = decltype(AA)::value;
+                static_for<0, a + 1>([&](auto BB) {
+                    constexpr int b = decltype(BB)::value;
+                    constexpr bool ha = in_set(a, LO, HI), hb = in_set(b, LO, HI);
+                    if constexpr (ha || hb) {
+                        constexpr int n = pass_slot(M, LO, HI, a, b);
+                        float2 sum;
+                        if constexpr (a == 0) {
+                            sum = Y[c][0];
+                        } else if constexpr (a == b) {
+                            sum = c_add(Y[c + a][a - LO], Y[c - a][a - LO]);
+                        } else if constexpr (b == 0) {
+                            if constexpr (ha && hb)
+                                sum = c_add(Y[c][a - LO], c_add(Y[c + a][0], Y[c - a][0]));
+                            else if constexpr (ha)
+                                sum = Y[c][a - LO];
+                            else
+                                sum = c_add(Y[c + a][0], Y[c - a][0]);
+                        } else {
+                            if constexpr (ha && hb)
+                                sum = c_add(c_add(Y[c + b][a - LO], Y[c - b][a - LO]),
+                                            c_add(Y[c + a][b - LO], Y[c - a][b - LO]));
+                            else if constexpr (ha)
+                                sum = c_add(Y[c + b][a - LO], Y[c - b][a - LO]);
+                            else
+                                sum = c_add(Y[c + a][b - LO], Y[c - a][b - LO]);
+                        }
+                        o = c_fma(h[n], sum, o);
+                    }
+                });
+            });
+            if constexpr (LAST) {
+                img[r] += (double)o.x;
+                buf_store_c64(rq, qbase + r * ny8, o);
+            } else {
+                // Pin the partial sum here: otherwise the compiler sinks this
+                // pass's arithmetic to its use in the next pass and keeps the
+                // whole pair-sum window of every row alive until then.
+                __asm__ volatile("" : "+v"(o.x), "+v"(o.y));
+                acc[r] = o;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+template <int M>
+__global__ void __launch_bounds__(kThreads3) __attribute__((amdgpu_waves_per_eu(2)))
+k_step3d(Step3dArgs A)
+{
+    constexpr int W = kLanes3 + 2 * M;       // LDS tile row length (with halo)
+    constexpr int H = kTileX3 + 2 * M;       // LDS tile rows (with halo)
+    constexpr int HP = (H + kWaves3 - 1) / kWaves3 * kWaves3;  // padded to whole wave rounds
+    constexpr int SPLIT = M >= 3 ? (M + 1) / 2 : M + 1;  // planes of the first pass
+    __shared__ float2 T[HP * W];
+    __shared__ double S[kTileX3 * kLanes3];
+
+    const int ntiles = A.tiles_x * A.tiles_y;
+    const int bid = logical_block();
+    const int g = bid / ntiles, t = bid % ntiles;
+    const int x0 = (t / A.tiles_y) * kTileX3, y0 = (t % A.tiles_y) * kLanes3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t plane = (size_t)A.nx * A.ny;
+    const int y = y0 + lane;
+    const int r0 = wave * kRows3;
+
+    for (int e = threadIdx.x; e < kTileX3 * kLanes3; e += kThreads3) {
+        const int x = x0 + e / kLanes3, yy = y0 + e % kLanes3;
+        S[e] = (x < A.nx && yy < A.ny) ? slowness_of(A.vel[(size_t)x * A.ny + yy])
+                                       : __builtin_nan("");
+    }
+
+    double img[kRows3];
+#pragma unroll
+    for (int r = 0; r < kRows3; ++r) img[r] = 0.0;
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)A.tab, 0, A.nk * ((M + 1) * (M + 2) / 2) * (int)sizeof(float2), kRawBufferWord3);
+
+    const int wbeg = g * A.wpg;
+    const int wend = wbeg + A.wpg < A.nw ? wbeg + A.wpg : A.nw;
+    // Columns this lane stages: y0 - M + lane and, for the first 2M lanes,
+    // the right halo 64 columns further; outside [0, ny) they stage zeros.
+    const int yc = y0 - M + lane, yc2 = yc + kLanes3;
+    const bool ym = yc >= 0 && yc < A.ny;
+    const bool yh = lane < 2 * M && yc2 < A.ny;
+    const int ny8 = A.ny * 8;
+    // Byte offset of this lane's first output within a plane.  Rows at or
+    // past nx land past the plane's end by themselves; a column past ny is
+    // moved out of range as a whole (stores out of range are dropped).
+    const int qbase = y < A.ny ? (x0 + r0) * ny8 + y * 8 : 0x40000000;
+    for (int w = wbeg; w < wend; ++w) {
+        // Rows outside [0, nx) fall outside the buffer's range and load zeros.
+        const __amdgpu_buffer_rsrc_t rp =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)w * plane), 0,
+                                              (int)(plane * sizeof(float2)), kRawBufferWord3);
+        __syncthreads();  // the previous frequency's tile is no longer read
+#pragma unroll
+        for (int q = 0; q < HP / kWaves3; ++q) {
+            // rows H..HP-1 are padding: staged but never read
+            const int r = q * kWaves3 + wave;
+            const int xo = (x0 - M + r) * ny8;
+            const float2 v = buf_load_c64(rp, xo + yc * 8);
+            const float2 v2 = buf_load_c64(rp, xo + yc2 * 8);
+            T[r * W + lane] = ym ? v : make_float2(0.0f, 0.0f);
+            if (lane < 2 * M) T[r * W + kLanes3 + lane] = yh ? v2 : make_float2(0.0f, 0.0f);
+        }
+        __syncthreads();
+
+        const double ar = A.omega[w] / A.dk;
+        const float2* Tw = T + r0 * W + lane + M;  // tile row of x0 + r0 - M, column y
+        const __amdgpu_buffer_rsrc_t rq =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(A.out + (size_t)w * plane), 0,
+                                              (int)(plane * sizeof(float2)), kRawBufferWord3);
+        float2 acc[kRows3];
+#pragma unroll
+        for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
+        if constexpr (SPLIT <= M) {
+            fir_pass<M, 0, SPLIT, false>(Tw, S, lane, r0, ar, A, rt, acc, img, rq, qbase, ny8);
+            fir_pass<M, SPLIT, M + 1, true>(Tw, S, lane, r0, ar, A, rt, acc, img, rq, qbase, ny8);
+        } else {
+            fir_pass<M, 0, M + 1, true>(Tw, S, lane, r0, ar, A, rt, acc, img, rq, qbase, ny8);
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < kRows3; ++r) {
+        const int x = x0 + r0 + r;
+        if (x < A.nx && y < A.ny) A.part[(size_t)g * plane + (size_t)x * A.ny + y] = img[r];
+    }
+
+    // Image row of the previous depth step: this workgroup's share of the
+    // tile, groups added in group order.
+    if (A.prev) {
+        constexpr int pts = kTileX3 * kLanes3;
+        const int share = (pts + A.ngroups - 1) / A.ngroups;
+        const int e1 = (g + 1) * share < pts ? (g + 1) * share : pts;
+        for (int e = g * share + threadIdx.x; e < e1; e += kThreads3) {
+            const int x = x0 + e / kLanes3, yy = y0 + e % kLanes3;
+            if (x < A.nx && yy < A.ny) {
+                const size_t p = (size_t)x * A.ny + yy;
+                double s = 0.0;
+                for (int q = 0; q < A.ngroups; ++q) s += A.prev[(size_t)q * plane + p];
+                A.prev_row[p] = s;
+            }
+        }
+    }
+}
+
+// Image of a plane: row[p] = sum over frequencies, in order, of Re wf[w][p].
+__global__ void k_image3d(const float2* __restrict__ wf, double* __restrict__ row, size_t plane,
+                          int nw)
+{
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane;
+         p += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += (double)wf[(size_t)w * plane + p].x;
+        row[p] = s;
+    }
+}
+
+// row[p] = sum over groups, in order, of part[g][p].
+__global__ void k_reduce3d(const double* __restrict__ part, double* __restrict__ row, size_t plane,
+                           int ngroups)
+{
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane;
+         p += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < ngroups; ++q) s += part[(size_t)q * plane + p];
+        row[p] = s;
+    }
+}
+
+unsigned grid_for(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    return (unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+int step3d_tiles_x(int nx) { return (nx + kTileX3 - 1) / kTileX3; }
+int step3d_tiles_y(int ny) { return (ny + kLanes3 - 1) / kLanes3; }
+
+int launch_step3d(const Step3dArgs& a, int M, hipStream_t s)
+{
+    const unsigned nb = (unsigned)(a.tiles_x * a.tiles_y * a.ngroups);
+    switch (M) {
+    case 0: hipLaunchKernelGGL(k_step3d<0>, dim3(nb), dim3(kThreads3), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_step3d<1>, dim3(nb), dim3(kThreads3), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_step3d<2>, dim3(nb), dim3(kThreads3), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_step3d<3>, dim3(nb), dim3(kThreads3), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_step3d<4>, dim3(nb), dim3(kThreads3), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_step3d<5>, dim3(nb), dim3(kThreads3), 0, s, a); break;
+    default: return MIG_E_ARG;
+    }
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+int launch_image3d(const float2* wf, double* row, size_t plane, int nw, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_image3d, dim3(grid_for(plane)), dim3(256), 0, s, wf, row, plane, nw);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+int launch_reduce3d(const double* part, double* row, size_t plane, int ngroups, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce3d, dim3(grid_for(plane)), dim3(256), 0, s, part, row, plane,
+                       ngroups);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+}  // namespace mig

@@ -97,6 +97,11 @@ def lib():
         "mig_batch_workspace_size": ([C.POINTER(CSection), i32, D, C.POINTER(CTuning)], sz),
         "mig_migrate_batched": ([C.POINTER(CSection), i32, P, D, C.POINTER(CTuning), P, sz, P],
                                 C.c_int),
+        "mig_design2d_workspace_size": ([D], sz),
+        "mig_design_table_2d": ([D, P, P, P, P, P, sz, P], C.c_int),
+        "mig_omegas_per_group_3d": ([i32, i32, i32, i32], C.c_int),
+        "mig_migrate3d_workspace_size": ([i32, i32, i32, i32, i32], sz),
+        "mig_migrate3d": ([P, P, P, P, D, i32, i32, i32, i32, i32, P, P, P, sz, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)   # AttributeError: the built library is older than this binding
@@ -359,3 +364,64 @@ def transform_t(section, dt, omega, out=None, ws=None):
 def migrate_tx(section, dt, vel, omega, tab32, desc, ws=None):
     """Algorithm 1 from a t-x section: transform along t, then migrate."""
     return migrate(transform_t(section, dt, omega), vel, omega, tab32, desc, ws=ws)
+
+
+# --------------------------------------------------------------------------- #
+# 3-D extension: circularly symmetric 2-D extrapolators.
+# --------------------------------------------------------------------------- #
+def design_table_2d(desc, device="cuda", ws=None):
+    """2-D table: dict(tab64 [nk][NU] complex128, tab32 complex64, maxgain, passerr),
+    NU = (M+1)(M+2)/2 unique coefficients c(a, b), a >= b, at a(a+1)/2 + b."""
+    cd = cdesc(desc)
+    M = (desc.ntaps - 1) // 2
+    NU = (M + 1) * (M + 2) // 2
+    dev = torch.device(device)
+    tab64 = torch.empty((desc.nk, NU), dtype=torch.complex128, device=dev)
+    tab32 = torch.empty((desc.nk, NU), dtype=torch.complex64, device=dev)
+    mg = torch.empty(desc.nk, dtype=torch.float64, device=dev)
+    pe = torch.empty(desc.nk, dtype=torch.float64, device=dev)
+    need = int(lib().mig_design2d_workspace_size(C.byref(cd)))
+    if need == 0:
+        raise MigError(-1, "mig_design2d_workspace_size: descriptor out of range")
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    rc = lib().mig_design_table_2d(C.byref(cd), _p(tab64), _p(tab32), _p(mg), _p(pe), _p(ws),
+                                   ws.numel(), _stream())
+    _check(rc, "mig_design_table_2d")
+    return {"tab64": tab64, "tab32": tab32, "maxgain": mg, "passerr": pe}
+
+
+def omegas_per_group_3d(nx, ny, nw, want=0) -> int:
+    return int(lib().mig_omegas_per_group_3d(nx, ny, nw, want))
+
+
+def migrate3d_workspace_size(nx, ny, nw, nz, omegas_per_group=0) -> int:
+    return int(lib().mig_migrate3d_workspace_size(nx, ny, nw, nz, omegas_per_group))
+
+
+def migrate3d(data, vel, omega, tab32, desc, omegas_per_group=0, ws=None, out=None,
+              plane_out=None):
+    """3-D migration.  data [nw][nx][ny] complex64, vel [nz][nx][ny] float32,
+    omega [nw] float64 -> image [nz][nx][ny] float64 (and the last plane into
+    plane_out [nw][nx][ny] complex64 when given)."""
+    nw, nx, ny = data.shape
+    nz = vel.shape[0]
+    _need(data, torch.complex64, (nw, nx, ny), "data")
+    _need(vel, torch.float32, (nz, nx, ny), "vel")
+    _need(omega, torch.float64, (nw,), "omega")
+    M = (desc.ntaps - 1) // 2
+    _need(tab32, torch.complex64, (desc.nk, (M + 1) * (M + 2) // 2), "tab32")
+    if out is None:
+        out = torch.empty((nz, nx, ny), dtype=torch.float64, device=data.device)
+    _need(out, torch.float64, (nz, nx, ny), "out")
+    if plane_out is not None:
+        _need(plane_out, torch.complex64, (nw, nx, ny), "plane_out")
+    if ws is None:
+        n = migrate3d_workspace_size(nx, ny, nw, nz, omegas_per_group)
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=data.device)
+    cd = cdesc(desc)
+    rc = lib().mig_migrate3d(_p(data), _p(vel), _p(omega), _p(tab32), C.byref(cd), nx, ny, nw,
+                             nz, omegas_per_group, _p(out), _p(plane_out), _p(ws), ws.numel(),
+                             _stream())
+    _check(rc, "mig_migrate3d")
+    return out

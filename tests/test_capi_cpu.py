@@ -91,3 +91,39 @@ def test_workspace_sizes_and_kernel_kinds(L):
     assert mig.kernel_kind(2049, 25) == 0
     assert mig.kernel_kind(512, 37) == 0
     assert mig.kernel_kind(512, 36) == -1
+
+
+def test_3d_host_checks_and_workspace_sizes(L):
+    from paper_1912_05529_amd import mig, synth
+    fake = C.c_void_p(4096)
+    d2 = synth.table2d_for(11, 64, 5.0, 40.0, 750.0, 2000.0, 10.0, 10.0)
+    # 2-D design workspace: basis on the design grid, cosines on the check
+    # grid, one status word per entry (each region 256-byte aligned)
+    al = lambda n: (n + 255) // 256 * 256
+    assert L.mig_design2d_workspace_size(C.byref(mig.cdesc(d2))) == (
+        al(48 * 48 * 21 * 8) + al(192 * 6 * 8) + al(64 * 4))
+    for bad in (dict(ntaps=13), dict(ngrid=65), dict(ncheck=4097)):
+        import dataclasses
+        cd = mig.cdesc(dataclasses.replace(d2, **bad))
+        assert L.mig_design2d_workspace_size(C.byref(cd)) == 0
+        assert L.mig_design_table_2d(C.byref(cd), fake, None, None, None, fake, 1 << 30,
+                                     None) == -1
+    # migration workspace: two planes + two groups of partial image slices
+    nx, ny, nw = 100, 70, 13
+    for wpg in (1, 4, 13, 50):
+        ng = (nw + min(wpg, nw) - 1) // min(wpg, nw)
+        assert mig.omegas_per_group_3d(nx, ny, nw, wpg) == min(wpg, nw)
+        assert mig.migrate3d_workspace_size(nx, ny, nw, 5, wpg) == (
+            2 * al(nx * ny * nw * 8) + 2 * al(ng * nx * ny * 8))
+    assert mig.migrate3d_workspace_size(0, 8, 2, 3) == 0
+    assert mig.migrate3d_workspace_size(8, 8, 2, 0) == 0
+    assert mig.omegas_per_group_3d(8, 8, 2, -1) == -1
+    cd = mig.cdesc(d2)
+    # NULL data, too-wide filters, too-small workspace
+    assert L.mig_migrate3d(None, fake, fake, fake, C.byref(cd), 8, 8, 2, 3, 0, fake, None, fake,
+                           1 << 30, None) == -1
+    wide = mig.cdesc(synth.table2d_for(13, 64, 5.0, 40.0, 750.0, 2000.0, 10.0, 10.0))
+    assert L.mig_migrate3d(fake, fake, fake, fake, C.byref(wide), 8, 8, 2, 3, 0, fake, None,
+                           fake, 1 << 30, None) == -1
+    assert L.mig_migrate3d(fake, fake, fake, fake, C.byref(cd), 8, 8, 2, 3, 1, C.c_void_p(1 << 40),
+                           None, C.c_void_p(1 << 41), 16, None) == -4

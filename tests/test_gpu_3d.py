@@ -1,0 +1,188 @@
+"""3-D extension through the C ABI: 2-D table design and migration of volumes
+against the FP64 oracle.
+
+Tolerances.  The table is compared as the 2-D sections' tables are: within
+four times the oracle's own sensitivity to 1-ulp changes of its inputs (the
+WLS map is ill-conditioned).  Wavefields are FP32: each depth step rounds a
+sum of (2M+1)^2 products, so the error relative to the plane's largest value
+grows about linearly with the number of steps; the bound used is
+8e-7 * (steps + 1) * NU of that largest value (NU = unique coefficients), and
+images (FP64 sums of FP32 values) are held to the same bound relative to
+their largest value.  Integer decisions (table entries) are taken in FP64 on
+both sides, so they agree exactly.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1912_05529_amd import mig, synth
+from gpu_helpers import dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _ulp_sensitivity_2d(desc, ot):
+    worst = 0.0
+    for kw in ({"dx": np.nextafter(desc.dx, np.inf), "dz": np.nextafter(desc.dz, np.inf)},
+               {"tau": np.nextafter(desc.tau, np.inf)}):
+        t1 = oracle.design_table_2d(dataclasses.replace(desc, **kw))[0]
+        worst = max(worst, float(np.abs(t1 - ot).max() / np.abs(ot).max()))
+    return worst
+
+
+@pytest.fixture(scope="module")
+def cfg5_desc():
+    return synth.config5(with_data=False).desc
+
+
+@pytest.fixture(scope="module")
+def tables2d():
+    cache = {}
+
+    def get(desc):
+        if desc not in cache:
+            cache[desc] = (oracle.design_table_2d(desc), mig.design_table_2d(desc, dev()))
+        return cache[desc]
+    return get
+
+
+def _vol_tensors(vol):
+    d = dev()
+    data = np.ascontiguousarray(np.moveaxis(vol.data.astype(np.complex64), 2, 0))
+    return (torch.from_numpy(data).to(d), torch.from_numpy(np.ascontiguousarray(vol.vel)).to(d),
+            torch.from_numpy(vol.omega).to(d))
+
+
+def _data64(vol):
+    return vol.data.astype(np.complex64).astype(np.complex128)
+
+
+def _tol(desc, steps):
+    M = (desc.ntaps - 1) // 2
+    nu = (M + 1) * (M + 2) // 2
+    return 8e-7 * (steps + 1) * nu
+
+
+@pytest.mark.parametrize("which", ["cfg5", "point", "small5"])
+def test_design2d_matches_oracle(which, tables2d, cfg5_desc):
+    desc = {"cfg5": cfg5_desc, "point": synth.point_scatterer_3d().desc,
+            "small5": synth.random_volume(1, 4, 4, 2, 2, ntaps=5, nk=32).desc}[which]
+    (ot, omg, ope, _), g = tables2d(desc)
+    t64 = g["tab64"].cpu().numpy()
+    err = np.abs(t64 - ot).max() / np.abs(ot).max()
+    sens = _ulp_sensitivity_2d(desc, ot)
+    tol = 4.0 * sens + 1e-12
+    print("%s 2-D table max rel diff %.3e; oracle 1-ulp sensitivity %.3e" % (which, err, sens))
+    assert tol < 6e-8
+    assert err <= tol
+    assert np.abs(g["maxgain"].cpu().numpy() - omg).max() <= tol
+    assert np.abs(g["passerr"].cpu().numpy() - ope).max() <= tol
+    assert float(g["maxgain"].max()) <= 1.0
+    assert torch.equal(g["tab32"], g["tab64"].to(torch.complex64))
+
+
+def _check_volume(vol, tab64_np, tab32, wpg=0):
+    data, vel, om = _vol_tensors(vol)
+    plane = torch.empty_like(data)
+    img = mig.migrate3d(data, vel, om, tab32, vol.desc, omegas_per_group=wpg, plane_out=plane)
+    torch.cuda.synchronize()
+    ref_img, ref_plane = oracle.migrate3d(vol.desc, tab64_np, vol.omega, vol.vel, _data64(vol),
+                                          want_plane=True)
+    tol = _tol(vol.desc, vol.nz - 1)
+    got_plane = np.moveaxis(plane.cpu().numpy(), 0, 2)
+    perr = np.abs(got_plane - ref_plane).max() / max(np.abs(ref_plane).max(), 1e-300)
+    ierr = np.abs(img.cpu().numpy() - ref_img).max() / max(np.abs(ref_img).max(), 1e-300)
+    print("%s wpg=%d: plane err %.3e image err %.3e (tol %.1e)" % (vol.name, wpg, perr, ierr, tol))
+    assert perr <= tol and ierr <= tol
+    return img, plane
+
+
+CASES = [
+    # nx, ny, nz, nw, ntaps, layered, omegas per group
+    (33, 70, 6, 5, 11, True, 0),
+    (64, 64, 5, 8, 11, False, 3),
+    (32, 64, 4, 3, 11, False, 1),
+    (1, 1, 4, 3, 11, False, 0),
+    (100, 1, 5, 4, 9, True, 2),
+    (1, 130, 4, 2, 7, False, 0),
+    (17, 129, 4, 3, 5, False, 0),
+    (40, 65, 3, 4, 3, True, 4),
+    (20, 20, 3, 2, 1, False, 0),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,nw,ntaps,layered,wpg", CASES)
+def test_migrate3d_matches_oracle(nx, ny, nz, nw, ntaps, layered, wpg):
+    vol = synth.random_volume(700 + nx + ny, nx, ny, nz, nw, ntaps=ntaps, nk=64, layered=layered)
+    ot = oracle.design_table_2d(vol.desc)[0]
+    tab32 = torch.from_numpy(ot.astype(np.complex64)).to(dev())
+    _check_volume(vol, ot, tab32, wpg)
+
+
+def test_point_scatterer_focuses_and_matches_oracle(tables2d):
+    vol = synth.point_scatterer_3d()
+    (ot, _, _, _), g = tables2d(vol.desc)
+    img, _ = _check_volume(vol, g["tab64"].cpu().numpy(), g["tab32"])
+    im = img.cpu().numpy()
+    k, x, y = np.unravel_index(np.argmax(np.abs(im)), im.shape)
+    e = vol.extra
+    assert abs(k - e["iz0"]) <= 1 and abs(x - e["ix0"]) <= 1 and abs(y - e["iy0"]) <= 1
+
+
+def test_grouping_changes_only_the_image_sum_order():
+    vol = synth.random_volume(77, 48, 96, 5, 12, ntaps=11, nk=64)
+    ot = oracle.design_table_2d(vol.desc)[0]
+    tab32 = torch.from_numpy(ot.astype(np.complex64)).to(dev())
+    data, vel, om = _vol_tensors(vol)
+    planes, imgs = [], []
+    for wpg in (1, 5, 12, 0, 5):
+        p = torch.empty_like(data)
+        imgs.append(mig.migrate3d(data, vel, om, tab32, vol.desc, omegas_per_group=wpg,
+                                  plane_out=p))
+        planes.append(p)
+    for p in planes[1:]:
+        assert torch.equal(p, planes[0])
+    assert torch.equal(imgs[1], imgs[4])         # same grouping: bit-identical
+    scale = float(imgs[0].abs().max())
+    for im in imgs[1:]:
+        assert float((im - imgs[0]).abs().max()) <= 1e-12 * scale
+
+
+def test_single_depth_is_image_of_data():
+    vol = synth.random_volume(78, 9, 70, 1, 6, ntaps=11, nk=64)
+    ot = oracle.design_table_2d(vol.desc)[0]
+    tab32 = torch.from_numpy(ot.astype(np.complex64)).to(dev())
+    data, vel, om = _vol_tensors(vol)
+    p = torch.empty_like(data)
+    img = mig.migrate3d(data, vel, om, tab32, vol.desc, plane_out=p)
+    assert torch.equal(p, data)
+    ref = np.sum(_data64(vol).real, axis=2)
+    assert np.abs(img[0].cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_config5_full_size_first_steps_match_oracle(tables2d, cfg5_desc):
+    """Full lateral size and frequency count, in the launch configuration the
+    benchmark uses (library-chosen grouping), over the first 4 depth slices."""
+    vol = synth.config5()
+    vol.vel = np.ascontiguousarray(vol.vel[:4])
+    vol.nz = 4
+    (ot, _, _, _), g = tables2d(vol.desc)
+    _check_volume(vol, g["tab64"].cpu().numpy(), g["tab32"])
+
+
+def test_error_paths():
+    vol = synth.random_volume(79, 8, 8, 3, 2, ntaps=11, nk=16)
+    ot = oracle.design_table_2d(vol.desc)[0]
+    tab32 = torch.from_numpy(ot.astype(np.complex64)).to(dev())
+    data, vel, om = _vol_tensors(vol)
+    with pytest.raises(mig.MigError):
+        mig.migrate3d(data, vel, om, tab32, vol.desc,
+                      ws=torch.empty(16, dtype=torch.uint8, device=dev()))
+    big = dataclasses.replace(vol.desc, ntaps=13)
+    with pytest.raises(mig.MigError):
+        mig.design_table_2d(big, dev())
+    assert mig.migrate3d_workspace_size(0, 8, 2, 3) == 0
+    assert mig.omegas_per_group_3d(8, 8, 2, -1) == -1
