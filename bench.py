@@ -1,21 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of explicit f-x poststack depth migration on one MI355X.
 
-Workload: the 2-D laterally varying section (nx=1024, nz=512, dx=dz=10 m,
-200 frequencies 5-55 Hz, 6-10 dipping layers 1500-4500 m/s plus a 4800 m/s
-body, 35-tap extrapolators, 2048-entry table), seeded synthetic inputs.
+Headline workload: the 2-D laterally varying section (nx=1024, nz=512,
+dx=dz=10 m, 200 frequencies 5-55 Hz, 6-10 dipping layers 1500-4500 m/s plus
+a 4800 m/s body, 35-tap extrapolators, 2048-entry table), seeded synthetic
+inputs.
 
 One step = Algorithm 1 end to end on the section, inputs resident in HBM:
 image row 0, then all 511 depth steps of Eq. (1) with FP32 complex
-wavefields, per-point table look-up, and FP64 image rows (mig_migrate).
-The table is designed once on the GPU beforehand (reported as design_ms).
+wavefields, per-point table look-up, and FP64 image rows (the two C-ABI
+stages of mig_migrate).  The table is designed once on the GPU beforehand
+(reported as design_ms).
 
 Prints ONE JSON line.  value = G complex tap-MAC/s = nx*nw*(nz-1)*N / t.
-roofline: the extrapolation kernel's algorithmic FP32 FLOP per launch
+roofline: the depth-stepping launch's algorithmic FP32 FLOP
 (nx*nw*(nz-1)*(8(M+1)+2M)) over its event-timed average duration, against
 the MI355X FP32 vector peak.  cpu_baseline: the FP64 oracle on the host
-cores (this is also where the FP64 reference image for the error comes
-from).
+cores (also the FP64 reference for the image error).
+
+Extras on the same line (each against the plain per-section GPU path):
+  batched  - 64 sections of uneven size in the batched form with autotuned
+             knobs, vs 64 separate mig_migrate calls;
+  adjoint  - demigration (the adjoint) vs migration on the headline model,
+             the dot-product test at full size, and CGLS least-squares
+             migration (10 iterations, 5 % noise);
+  volume3d - the 3-D extension on a 256 x 256 x 200 volume with 128
+             frequencies and 11 x 11 circularly symmetric extrapolators,
+             with the FP64 oracle timed on its first depth steps.
 """
 from __future__ import annotations
 
@@ -40,29 +51,53 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip the FP64 oracle leg (no image error, no cpu_baseline)")
+                    help="skip the FP64 oracle legs (no image error, no cpu_baseline)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no batched / adjoint / 3-D extras)")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with rocprofv3-derived HBM bytes per launch")
-    ap.add_argument("--profile-only", action="store_true",
-                    help="short run for profilers: warmup + steps, no oracle, no JSON extras")
+    ap.add_argument("--profile", choices=["plain", "batched", "adjoint", "volume3d"],
+                    default=None,
+                    help="short run of one part for profilers: warmup + steps, no oracle, "
+                         "prints timings only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
-        sys.exit(2)
+class Timer:
+    """Event pair on the current stream."""
 
-    import torch
-    from paper_1912_05529_amd import mig, synth
+    def __init__(self, torch):
+        self.t = torch
+        self.s = torch.cuda.current_stream()
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
 
-    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
-    dev = torch.device("cuda:0")
+    def __enter__(self):
+        self.e0.record(self.s)
+        return self
+
+    def __exit__(self, *a):
+        self.e1.record(self.s)
+        self.e1.synchronize()
+        self.ms = self.e0.elapsed_time(self.e1)
+
+
+def timed(torch, fn, reps, warmup=1):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    with Timer(torch) as t:
+        for _ in range(reps):
+            fn()
+    return t.ms / reps
+
+
+# --------------------------------------------------------------------------- #
+# Headline: configuration 2, plain path.
+# --------------------------------------------------------------------------- #
+def headline(torch, mig, synth, dev, args):
     t_gen = time.time()
     sec = synth.config2()
     gen_s = time.time() - t_gen
@@ -74,17 +109,13 @@ def main():
     omega = torch.from_numpy(sec.omega).to(dev)
     stream = torch.cuda.current_stream()
 
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record(stream)
-    tab = mig.design_table(desc, dev)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    design_ms = e0.elapsed_time(e1)
+    with Timer(torch) as t:
+        tab = mig.design_table(desc, dev)
+    design_ms = t.ms
 
     ws = torch.empty(mig.workspace_size(nx, nz - 1, nw, desc), dtype=torch.uint8, device=dev)
     img = torch.empty((nz, nx), dtype=torch.float64, device=dev)
-
     rows_view = img[1:]
 
     # One step = mig_migrate's two C-ABI stages, called separately so that the
@@ -106,18 +137,15 @@ def main():
         step()
     torch.cuda.synchronize()
     t0 = time.time()
-    e0.record(stream)
-    for i in range(args.steps):
-        step(ev[i])
-    e1.record(stream)
-    torch.cuda.synchronize()
+    with Timer(torch) as t:
+        for i in range(args.steps):
+            step(ev[i])
     wall = time.time() - t0
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step = t.ms / args.steps
     ms_kernel = sum(a.elapsed_time(b) for a, b in ev) / args.steps
-    print("timed %d steps: %.3f ms/step (events), %.3f ms/step (wall), depth-stepping launch "
-          "%.3f ms" % (args.steps, ms_step, 1e3 * wall / args.steps, ms_kernel),
+    print("plain: %d steps, %.3f ms/step (events), %.3f ms/step (wall), depth-stepping "
+          "launch %.3f ms" % (args.steps, ms_step, 1e3 * wall / args.steps, ms_kernel),
           file=sys.stderr, flush=True)
-    # same result as the single-call entry point
     ref_img = mig.migrate(data, vel, omega, tab["tab32"], desc, ws=ws)
     assert torch.equal(ref_img, img), "staged step differs from mig_migrate"
     if args.calib_copy:
@@ -127,9 +155,6 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-    if args.profile_only:
-        print(json.dumps({"ms_per_step": ms_step, "ms_kernel": ms_kernel}))
-        return
 
     outputs = nx * nw * (nz - 1)
     tap_macs = outputs * N
@@ -140,7 +165,6 @@ def main():
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as f:
             traffic = json.load(f).get("bytes_per_launch")
-
     res = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -177,7 +201,6 @@ def main():
             "flop_per_launch": flop_alg,
         },
     }
-
     if not args.no_cpu_baseline:
         # cpu_baseline leg: the FP64 oracle, as it stands, on the host cores.
         import oracle
@@ -185,10 +208,13 @@ def main():
         t0 = time.time()
         otab = oracle.design_table(desc)[0]
         t_design = time.time() - t0
-        t0 = time.time()
-        ref = oracle.migrate(desc, otab, sec.omega, sec.vel,
-                             sec.data.astype(np.complex64).astype(np.complex128))
-        t_mig = time.time() - t0
+        d64 = sec.data.astype(np.complex64).astype(np.complex128)
+        times = []
+        for _ in range(3):   # median of three runs of the full workload
+            t0 = time.time()
+            ref = oracle.migrate(desc, otab, sec.omega, sec.vel, d64)
+            times.append(time.time() - t0)
+        t_mig = sorted(times)[1]
         gimg = img.cpu().numpy()
         res["image_rel_l2_vs_fp64"] = float(np.linalg.norm(gimg - ref) / np.linalg.norm(ref))
         res["cpu_baseline"] = {
@@ -196,12 +222,248 @@ def main():
             "unit": "G complex tap-MAC/s",
             "cores": omp,
             "kind": "oracle",
-            "sample": "the full workload once (all 200 frequencies, 511 depth steps, "
-                      "unfolded FP64 Eq. 1, OpenMP over frequencies); table design "
-                      "%.1f s not included" % t_design,
+            "sample": "the full workload (all 200 frequencies, 511 depth steps, unfolded "
+                      "FP64 Eq. 1, OpenMP over frequencies), median of 3 runs; table "
+                      "design %.1f s not included" % t_design,
             "seconds": round(t_mig, 3),
         }
         res["speedup_vs_cpu_oracle"] = round(value / res["cpu_baseline"]["value"], 1)
+    ctx = {"sec": sec, "tab": tab, "data": data, "vel": vel, "omega": omega, "ws": ws,
+           "ms_plain": ms_step}
+    return res, ctx
+
+
+# --------------------------------------------------------------------------- #
+# Batched form: configuration 3.
+# --------------------------------------------------------------------------- #
+def batched(torch, mig, synth, dev, args, profile=False):
+    from paper_1912_05529_amd import tune
+    secs = synth.config3()
+    desc = secs[0].desc
+    tab = mig.design_table(desc, dev)
+    batch = [{"data": torch.from_numpy(s.data.astype(np.complex64)).to(dev),
+              "vel": torch.from_numpy(s.vel).to(dev),
+              "omega": torch.from_numpy(s.omega).to(dev)} for s in secs]
+    best, table = tune.autotune(batch, tab["tab32"], desc, reps=1)
+    ws_b = torch.empty(max(mig.batch_workspace_size(batch, desc, best), 1), dtype=torch.uint8,
+                       device=dev)
+    reps = max(1, args.steps // 4)
+    ms_b = timed(torch, lambda: mig.migrate_batched(batch, tab["tab32"], desc, tune=best,
+                                                    ws=ws_b), reps)
+    if profile:
+        print(json.dumps({"part": "batched", "ms": ms_b, "tune": best}))
+        return None
+    need = max(mig.workspace_size(b["data"].shape[0], b["vel"].shape[0] - 1,
+                                  b["data"].shape[1], desc) for b in batch)
+    ws_p = torch.empty(need, dtype=torch.uint8, device=dev)
+    outs = [torch.empty_like(b["image"]) for b in batch]
+
+    def plain():
+        for b, o in zip(batch, outs):
+            mig.migrate(b["data"], b["vel"], b["omega"], tab["tab32"], desc, ws=ws_p, out=o)
+    ms_p = timed(torch, plain, reps)
+    plain()
+    mig.migrate_batched(batch, tab["tab32"], desc, tune=best, ws=ws_b)
+    torch.cuda.synchronize()
+    same = all(torch.equal(b["image"], o) for b, o in zip(batch, outs))
+    tap_macs = sum(s.nx * s.nw * (s.nz - 1) * desc.ntaps for s in secs)
+    out = {
+        "workload": "64 sections, seed-drawn nx 256-2048, nz 200-800, nw 100-300, 35-tap "
+                    "table, seed 3",
+        "ms_batched": round(ms_b, 3),
+        "ms_plain_64_calls": round(ms_p, 3),
+        "speedup_vs_plain": round(ms_p / ms_b, 3),
+        "G_tap_mac_per_s_batched": round(tap_macs / ms_b / 1e6, 1),
+        "G_tap_mac_per_s_plain": round(tap_macs / ms_p / 1e6, 1),
+        "tune": best,
+        "tune_candidates": len(table),
+        "images_bit_identical_to_plain": bool(same),
+    }
+    print("batched: %.3f ms vs plain %.3f ms (%s)" % (ms_b, ms_p, best), file=sys.stderr,
+          flush=True)
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# Adjoint and least-squares migration: configuration 2's model.
+# --------------------------------------------------------------------------- #
+def adjoint(torch, mig, synth, dev, args, ctx=None, profile=False):
+    from paper_1912_05529_amd import lsm
+    if ctx is None:
+        sec = synth.config2(with_data=False)
+        tab = mig.design_table(sec.desc, dev)
+        ctx = {"sec": sec, "tab": tab, "vel": torch.from_numpy(sec.vel).to(dev),
+               "omega": torch.from_numpy(sec.omega).to(dev)}
+    sec, tab, vel, omega = ctx["sec"], ctx["tab"], ctx["vel"], ctx["omega"]
+    desc = sec.desc
+    refl = torch.from_numpy(sec.extra["refl"]).to(dev)
+    nz, nx = refl.shape
+    ws_a = torch.empty(max(mig.demigrate_workspace_size(nx, nz, desc), 1), dtype=torch.uint8,
+                       device=dev)
+    d = torch.empty((nx, sec.nw), dtype=torch.complex64, device=dev)
+    reps = max(1, args.steps // 4)
+    ms_adj = timed(torch, lambda: mig.demigrate(refl, vel, omega, tab["tab32"], desc, out=d,
+                                                ws=ws_a), reps)
+    if profile:
+        print(json.dumps({"part": "adjoint", "ms": ms_adj}))
+        return None
+    ws_m = torch.empty(mig.workspace_size(nx, nz - 1, sec.nw, desc), dtype=torch.uint8,
+                       device=dev)
+    img = torch.empty((nz, nx), dtype=torch.float64, device=dev)
+    ms_fwd = timed(torch, lambda: mig.migrate(d, vel, omega, tab["tab32"], desc, ws=ws_m,
+                                              out=img), reps)
+    # dot-product test at full size: <A d, m> = <d, A^T m>
+    g = torch.Generator(device="cpu").manual_seed(9)
+    dd = (torch.randn((nx, sec.nw), generator=g) + 1j * torch.randn((nx, sec.nw), generator=g))
+    dd = dd.to(torch.complex64).to(dev)
+    mm = torch.randn((nz, nx), generator=g, dtype=torch.float64).to(dev)
+    Ad = mig.migrate(dd, vel, omega, tab["tab32"], desc)
+    Atm = mig.demigrate(mm, vel, omega, tab["tab32"], desc)
+    lhs = float(torch.sum(Ad * mm))
+    rhs = float(torch.sum(dd.real.double() * Atm.real.double() + dd.imag.double() * Atm.imag.double()))
+    dot_rel = abs(lhs - rhs) / (float(torch.linalg.norm(Ad)) * float(torch.linalg.norm(mm)))
+    # CGLS on the layered model's reflectivity with 5 % noise
+    d_clean = mig.demigrate(refl, vel, omega, tab["tab32"], desc)
+    rms = float(torch.sqrt(torch.mean(torch.abs(d_clean) ** 2)))
+    noise = (torch.randn(d_clean.shape, generator=g) + 1j * torch.randn(d_clean.shape, generator=g))
+    d_obs = d_clean + (0.05 * rms / np.sqrt(2.0) * noise).to(torch.complex64).to(dev)
+    torch.cuda.synchronize()
+    with Timer(torch) as t:
+        m, hist = lsm.cgls(d_obs, vel, omega, tab["tab32"], desc, niter=10)
+    err = float(torch.linalg.norm(m - refl) / torch.linalg.norm(refl))
+    out = {
+        "workload": "adjoint of the headline section's migration (reflectivity -> data), "
+                    "and CGLS least-squares migration with 5 % Gaussian noise, 10 iterations",
+        "ms_demigrate": round(ms_adj, 3),
+        "ms_migrate": round(ms_fwd, 3),
+        "adjoint_vs_plain_time": round(ms_adj / ms_fwd, 3),
+        "dot_product_rel_err": dot_rel,
+        "cgls_ms_total": round(t.ms, 2),
+        "cgls_residual_history": [round(h, 4) for h in hist],
+        "cgls_model_rel_err": round(err, 4),
+    }
+    print("adjoint: %.3f ms vs migrate %.3f ms; CGLS %.1f ms" % (ms_adj, ms_fwd, t.ms),
+          file=sys.stderr, flush=True)
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# 3-D extension: configuration 5.
+# --------------------------------------------------------------------------- #
+def volume3d(torch, mig, synth, dev, args, profile=False):
+    t0 = time.time()
+    vol = synth.config5(with_data=not profile)
+    gen_s = time.time() - t0
+    desc = vol.desc
+    nx, ny, nz, nw = vol.nx, vol.ny, vol.nz, vol.nw
+    M = (desc.ntaps - 1) // 2
+    nu = (M + 1) * (M + 2) // 2
+    if profile:
+        rng = np.random.default_rng(5)
+        vol.data = rng.standard_normal((nx, ny, nw)) + 1j * rng.standard_normal((nx, ny, nw))
+    data = torch.from_numpy(np.ascontiguousarray(
+        np.moveaxis(vol.data.astype(np.complex64), 2, 0))).to(dev)
+    vel = torch.from_numpy(vol.vel).to(dev)
+    omega = torch.from_numpy(vol.omega).to(dev)
+    with Timer(torch) as t:
+        tab = mig.design_table_2d(desc, dev)
+    design_ms = t.ms
+    ws = torch.empty(mig.migrate3d_workspace_size(nx, ny, nw, nz), dtype=torch.uint8, device=dev)
+    img = torch.empty((nz, nx, ny), dtype=torch.float64, device=dev)
+    reps = max(1, args.steps // 5)
+    ms = timed(torch, lambda: mig.migrate3d(data, vel, omega, tab["tab32"], desc, ws=ws, out=img),
+               reps)
+    if profile:
+        print(json.dumps({"part": "volume3d", "ms": ms}))
+        return None
+    outputs = nx * ny * nw * (nz - 1)
+    flop_out = 8 * nu + 2 * ((2 * M + 1) ** 2 - nu)   # folded form: unique MACs + orbit adds
+    achieved = outputs * flop_out / (ms * 1e-3) / 1e12
+    out = {
+        "workload": "3-D layered volume with an ellipsoidal body: nx=ny=256, nz=200, "
+                    "dx=dy=dz=10 m, 128 frequencies 5-40 Hz, 11x11 circularly symmetric "
+                    "extrapolators (21 unique taps), 1024-entry table, seed 5",
+        "ms_per_volume": round(ms, 3),
+        "us_per_depth_step": round(1e3 * ms / (nz - 1), 2),
+        "G_outputs_per_s": round(outputs / ms / 1e6, 2),
+        "G_tap_mac_per_s_nominal": round(outputs * (2 * M + 1) ** 2 / ms / 1e6, 1),
+        "design_ms": round(design_ms, 2),
+        "gen_s": round(gen_s, 2),
+        "omegas_per_group": mig.omegas_per_group_3d(nx, ny, nw, 0),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "3-D depth step (one launch per step), averaged over the volume "
+                      "including the image and reduction launches",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "flop_per_output": flop_out,
+        },
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 3
+        otab = tab["tab64"].cpu().numpy()
+        t0 = time.time()
+        ref = oracle.migrate3d(desc, otab, vol.omega, np.ascontiguousarray(vol.vel[:k + 1]),
+                               vol.data.astype(np.complex64).astype(np.complex128))
+        t_or = time.time() - t0
+        sub = torch.empty((k + 1, nx, ny), dtype=torch.float64, device=dev)
+        mig.migrate3d(data, vel[:k + 1].contiguous(), omega, tab["tab32"], desc, out=sub)
+        got = sub.cpu().numpy()
+        out["image_rel_l2_vs_fp64_first_steps"] = float(
+            np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["cpu_baseline"] = {
+            "value": round(nx * ny * nw * k / t_or / 1e9, 4),
+            "unit": "G outputs/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "the first %d depth steps of the volume (all frequencies, unfolded "
+                      "FP64 2-D Eq. 1)" % k,
+            "seconds": round(t_or, 3),
+        }
+        out["speedup_vs_cpu_oracle"] = round(out["G_outputs_per_s"] /
+                                             out["cpu_baseline"]["value"], 1)
+    print("volume3d: %.3f ms per volume (%.1f us/step)" % (ms, out["us_per_depth_step"]),
+          file=sys.stderr, flush=True)
+    return out
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_05529_amd import mig, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    dev = torch.device("cuda:0")
+
+    if args.profile == "batched":
+        batched(torch, mig, synth, dev, args, profile=True)
+        return
+    if args.profile == "adjoint":
+        adjoint(torch, mig, synth, dev, args, profile=True)
+        return
+    if args.profile == "volume3d":
+        volume3d(torch, mig, synth, dev, args, profile=True)
+        return
+    if args.profile == "plain":
+        args.no_cpu_baseline = True
+    res, ctx = headline(torch, mig, synth, dev, args)
+    if args.profile == "plain":
+        print(json.dumps({"part": "plain", "ms_per_step": res["ms_per_step"],
+                          "ms_kernel": res["roofline"]["ms_per_launch"]}))
+        return
+    if not args.no_extras:
+        res["batched"] = batched(torch, mig, synth, dev, args)
+        res["adjoint"] = adjoint(torch, mig, synth, dev, args, ctx)
+        res["volume3d"] = volume3d(torch, mig, synth, dev, args)
     print(json.dumps(res), flush=True)
 
 

@@ -74,13 +74,25 @@ int device_cus()
 }
 
 // Reducer workgroups beside `nprod` frequency workgroups: the CUs they leave
-// idle, at least 8, at most 64 and the number of reduction tasks.
-int reducer_count(int nprod, int ntasks, int want)
+// idle, at least 8, at most 64 (before capping by the number of tasks).
+int reducer_count(int nprod, int want)
 {
     int n = want > 0 ? want : device_cus() - nprod;
     if (n < 8) n = 8;
     if (n > 64) n = 64;
-    return n < ntasks ? n : ntasks;
+    return n;
+}
+
+int blocks_of(int nsteps) { return (nsteps + kPublish - 1) / kPublish; }
+
+// x-parts per published block: enough tasks for about two per reducer when
+// there are few blocks, parts at least 128 points wide.
+int parts_for(int total_blocks, int nred, int max_nx)
+{
+    int p = (2 * nred + total_blocks - 1) / total_blocks;
+    int cap = max_nx / 128 > 1 ? max_nx / 128 : 1;
+    if (p > cap) p = cap;
+    return p < 1 ? 1 : p;
 }
 
 // Frequencies per workgroup for one section in the register-tap kernel with two
@@ -156,8 +168,16 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
         a.one.vel = vel + (size_t)c0 * nx;
         a.one.nsteps = cs;
         a.one.rows = rows ? rows + (size_t)c0 * nx : nullptr;
-        a.ntasks = rows ? cs : 0;
-        a.nred = rows ? reducer_count(nitems, cs, tn.nred) : 0;
+        if (rows) {
+            const int nred = reducer_count(nitems, tn.nred);
+            a.parts = parts_for(blocks_of(cs), nred, nx);
+            a.ntasks = blocks_of(cs) * a.parts;
+            a.nred = nred < a.ntasks ? nred : a.ntasks;
+        } else {
+            a.parts = 1;
+            a.ntasks = 0;
+            a.nred = 0;
+        }
         int rc = launch_slowness(a, cs, ldp, flag_distance(kind), s);
         if (rc == MIG_OK && rows) rc = launch_zero(cnt, (cs + kPublish - 1) / kPublish, s);
         if (rc == MIG_OK) {
@@ -180,7 +200,7 @@ bool sizes_ok(int nx, int nw) { return nx >= 1 && nx <= MIG_MAX_NX && nw >= 1 &&
 struct BatchPlan {
     size_t bytes = 0;
     struct Group {
-        int kind = 0, threads = 0, max_nx = 0, max_rows = 0, max_ldp = 0;
+        int kind = 0, threads = 0, max_nx = 0, max_rows = 0, max_ldp = 0, nred = 0;
         std::vector<SecDev> secs;
         std::vector<ItemDev> items;
         std::vector<TaskDev> tasks;
@@ -265,10 +285,19 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
         });
         for (int si : order)
             for (int r0 = 0; r0 < g.secs[si].nw; r0 += g.secs[si].G) g.items.push_back(ItemDev{si, r0});
-        // Reducer tasks step-major across sections (production order).
-        for (int st = 0; st < g.max_rows; ++st)
-            for (int si : order)
-                if (st < g.secs[si].nsteps) g.tasks.push_back(TaskDev{si, st});
+        // Reducer tasks block-major across sections (production order).
+        int total_blocks = 0;
+        for (const SecDev& S : g.secs) total_blocks += blocks_of(S.nsteps);
+        g.nred = reducer_count((int)g.items.size(), tn.nred);
+        const int parts = parts_for(total_blocks, g.nred, g.max_nx);
+        for (int c = 0; c < blocks_of(g.max_rows); ++c)
+            for (int si : order) {
+                if (c >= blocks_of(g.secs[si].nsteps)) continue;
+                const int nx = g.secs[si].nx;
+                const int span = ((nx + parts - 1) / parts + 1) & ~1;
+                for (int x0 = 0; x0 < nx; x0 += span)
+                    g.tasks.push_back(TaskDev{si, c, x0, x0 + span < nx ? x0 + span : nx});
+            }
         g.desc_bytes = g.secs.size() * sizeof(SecDev) + g.items.size() * sizeof(ItemDev) +
                        g.tasks.size() * sizeof(TaskDev);
         g.desc_off = bump(off, g.desc_bytes);
@@ -314,7 +343,8 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
         a.nsec = (int)g.secs.size();
         a.nitems = (int)g.items.size();
         a.ntasks = (int)g.tasks.size();
-        a.nred = reducer_count(a.nitems, a.ntasks, tn.nred);
+        a.nred = g.nred < a.ntasks ? g.nred : a.ntasks;
+        a.parts = 1;
         a.nk = d->nk;
         a.M = M;
         a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);

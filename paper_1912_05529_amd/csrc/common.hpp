@@ -13,6 +13,8 @@ constexpr double kPi = 3.14159265358979323846;
 
 // Frequency workgroups publish their partial rows every kPublish depth steps.
 constexpr int kPublish = 16;
+// Reducers poll a block counter with this s_sleep argument (x 64 cycles).
+constexpr int kPollSleep = 127;
 // Reducers give up (and write NaN rows) after this long without progress.
 constexpr unsigned long long kStallTicks = 20ull * 100000000ull;  // 20 s at 100 MHz
 
@@ -36,15 +38,16 @@ struct ItemDev {
     int sec, r0;
 };
 
-// A reducer task: image row `step` of section `sec`.
+// A reducer task: image rows of the published block `block` (steps
+// block*kPublish ... +kPublish-1) of section `sec`, points [x0, x1).
 struct TaskDev {
-    int sec, step;
+    int sec, block, x0, x1;
 };
 
 // Arguments of one depth-stepping launch.  With nsec == 1 the section lives
 // in `one`, workgroup i owns frequencies [i*G, i*G+G) (G = one.G) and reducer
-// task i is step i; otherwise the three arrays (device memory) describe the
-// batch.
+// task i is part i % parts of block i / parts; otherwise the three arrays
+// (device memory) describe the batch.
 struct BatchArgs {
     SecDev one;
     const SecDev* secs;
@@ -53,6 +56,7 @@ struct BatchArgs {
     const float2* tab;     // [nk][M+1] complex64 half-taps
     float* trash;          // [ldp_max] sink for partial rows of idle sub-groups
     int nsec, nitems, ntasks, nred;
+    int parts;             // x-parts per block (nsec == 1)
     int nk, M;
     double dk;             // table spacing (kmax-kmin)/(nk-1)
     double b;              // kmin / dk

@@ -396,6 +396,10 @@ int launch_design2d(const mig_table_desc* d, const double* A, const double* CS,
     P.M = (d->ntaps - 1) / 2;
     P.K = (P.M + 1) * (P.M + 2) / 2;
     const size_t lds = (size_t)3 * d->ngrid * d->ngrid * sizeof(double);
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_design2d),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return MIG_E_DEVICE;
     hipLaunchKernelGGL(k_design2d, dim3(d->nk), dim3(kDesignThreads), lds, s, P, A, CS, tab64,
                        tab32, maxgain, passerr, status);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;

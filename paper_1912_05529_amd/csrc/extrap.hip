@@ -131,7 +131,11 @@ __device__ __forceinline__ ItemDev item_of(const BatchArgs& a, int i)
 
 __device__ __forceinline__ TaskDev task_of(const BatchArgs& a, int i)
 {
-    return a.nsec == 1 ? TaskDev{0, i} : a.tasks[i];
+    if (a.nsec != 1) return a.tasks[i];
+    const int p = i % a.parts;
+    const int span = ((a.one.nx + a.parts - 1) / a.parts + 1) & ~1;  // even part width
+    const int x0 = p * span;
+    return TaskDev{0, i / a.parts, x0, x0 + span < a.one.nx ? x0 + span : a.one.nx};
 }
 
 // Per-workgroup constants: frequencies per workgroup and sub-group size.
@@ -168,48 +172,50 @@ __global__ void k_slowness(BatchArgs a, int dist)
 __device__ __forceinline__ void publish_block(const SecDev& S, int c)
 {
     if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(S.cnt + c, 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(S.cnt + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// Reducer workgroup q of a.nred: tasks q, q + nred, ... (ordered step-major
-// across sections, i.e. in production order).
+// Reducer workgroup q of a.nred: tasks q, q + nred, ... (ordered block-major
+// across sections, i.e. in production order).  One wait and one acquire per
+// task: an acquire invalidates the L2 of the reducer's XCD, which the
+// frequency workgroups there pay for in table refills, so tasks are whole
+// published blocks (split along x only when there are few blocks).
 __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
 {
-    int seen_sec = -1, seen_c = -1;
-    bool ok = true;
     for (int i = q; i < a.ntasks; i += a.nred) {
         const TaskDev T = task_of(a, i);
         const SecDev S = sec_of(a, T.sec);
-        const int c = T.step / kPublish;
-        if (T.sec != seen_sec || c != seen_c) {
-            if (threadIdx.x == 0) {
-                int v, last = -1;
-                unsigned long long t0 = wall_clock64();
-                while ((v = __hip_atomic_load(S.cnt + c, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)) < S.nprod) {
-                    unsigned long long now = wall_clock64();
-                    if (v != last) {
-                        last = v;
-                        t0 = now;
-                    } else if (now - t0 > kStallTicks) {
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(8);
+        if (threadIdx.x == 0) {
+            int v, last = -1;
+            unsigned long long t0 = wall_clock64();
+            while ((v = __hip_atomic_load(S.cnt + T.block, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT)) < S.nprod) {
+                unsigned long long now = wall_clock64();
+                if (v != last) {
+                    last = v;
+                    t0 = now;
+                } else if (now - t0 > kStallTicks) {
+                    break;
                 }
-                __threadfence();
-                *flag = v >= S.nprod ? 1 : 0;
+                __builtin_amdgcn_s_sleep(kPollSleep);
             }
-            __syncthreads();
-            ok = *flag != 0;
-            __syncthreads();
-            seen_sec = T.sec;
-            seen_c = c;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            *flag = v >= S.nprod ? 1 : 0;
         }
-        const float* p = S.part + (size_t)T.step * S.nw * S.ldp;
-        double* row = S.rows + (size_t)T.step * S.nx;
-        for (int x0 = 2 * threadIdx.x; x0 < S.nx; x0 += 2 * blockDim.x) {
+        __syncthreads();
+        const bool ok = *flag != 0;
+        __syncthreads();
+        const int s0 = T.block * kPublish;
+        const int s1 = s0 + kPublish < S.nsteps ? s0 + kPublish : S.nsteps;
+        const int npair = (T.x1 - T.x0 + 1) / 2;
+        const int items = (s1 - s0) * npair;
+        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+            const int st = s0 + it / npair;
+            const int x0 = T.x0 + 2 * (it % npair);
+            const float* p = S.part + (size_t)st * S.nw * S.ldp;
+            double* row = S.rows + (size_t)st * S.nx;
             double a0 = 0.0, a1 = 0.0;
             int r = 0;
             for (; r + 8 <= S.nw; r += 8) {
@@ -230,8 +236,9 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
             }
             const double nan = __builtin_nan("");
             row[x0] = ok ? a0 : nan;
-            if (x0 + 1 < S.nx) row[x0 + 1] = ok ? a1 : nan;
+            if (x0 + 1 < T.x1) row[x0 + 1] = ok ? a1 : nan;
         }
+        __syncthreads();  // *flag is reused by the next task
     }
 }
 

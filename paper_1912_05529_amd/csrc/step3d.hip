@@ -60,23 +60,16 @@ __device__ __forceinline__ void buf_store_c64(__amdgpu_buffer_rsrc_t r, int byte
     __builtin_amdgcn_raw_buffer_store_b64(u, r, byte_off, 0, 0);
 }
 
+// s_waitcnt vmcnt(0), other counters left alone (GFX9 encoding:
+// vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] in bits 15:14).
+__device__ __forceinline__ void wait_vmem_all()
+{
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+}
+
 __device__ __forceinline__ float2 c_add(float2 a, float2 b)
 {
     return make_float2(a.x + b.x, a.y + b.y);
-}
-
-__device__ __forceinline__ float2 c_mul(float2 h, float2 u)
-{
-    return make_float2(fmaf(-h.y, u.y, h.x * u.x), fmaf(h.y, u.x, h.x * u.y));
-}
-
-__device__ __forceinline__ float2 c_fma(float2 h, float2 s, float2 acc)
-{
-    acc.x = fmaf(h.x, s.x, acc.x);
-    acc.x = fmaf(-h.y, s.y, acc.x);
-    acc.y = fmaf(h.x, s.y, acc.y);
-    acc.y = fmaf(h.y, s.x, acc.y);
-    return acc;
 }
 
 // Workgroup index -> (frequency group, tile).  Consecutive workgroup indices
@@ -130,9 +123,35 @@ __device__ __forceinline__ void static_for(F&& f)
 // The last pass also finishes each output at once: Re into the image
 // partial, and a buffer store whose offset is pushed out of range for
 // points outside the volume (so no output waits behind a branch).
+template <int M, int LO, int HI>
+__device__ __forceinline__ void load_pass_taps(float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)],
+                                               __amdgpu_buffer_rsrc_t rt, int j)
+{
+    constexpr int NU = (M + 1) * (M + 2) / 2;
+    const int toff = j * (NU * 8);
+    static_for<0, M + 1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        static_for<0, a + 1>([&](auto BB) {
+            constexpr int b = decltype(BB)::value;
+            if constexpr (in_set(a, LO, HI) || in_set(b, LO, HI))
+                h[pass_slot(M, LO, HI, a, b)] = buf_load_c64(rt, toff + cidx(a, b) * 8);
+        });
+    });
+}
+
+// Partial output of a pass: Re = re1 - re2 with re1 = sum Re h Re s and
+// re2 = sum Im h Im s kept apart (no negated operands), Im = sum of the
+// cross products.
+struct Acc3 {
+    float re1, re2, im;
+};
+
+// The last pass also finishes each output at once: Re into the image
+// partial, and a buffer store whose offset is pushed out of range for
+// points outside the volume (so no output waits behind a branch).
 template <int M, int LO, int HI, bool LAST>
-__device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const double* __restrict__ S,
-                                         int lane, int r0, double ar, const Step3dArgs& A,
+__device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const int (&jrow)[kRows3],
+                                         float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)], int& jcur,
                                          __amdgpu_buffer_rsrc_t rt, float2 (&acc)[kRows3],
                                          double (&img)[kRows3], __amdgpu_buffer_rsrc_t rq,
                                          int qbase, int ny8)
@@ -140,10 +159,6 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const do
     constexpr int W = kLanes3 + 2 * M;
     constexpr int NP = HI - LO;
     constexpr int NR = kRows3 + 2 * M;
-    constexpr int NC = pass_slot(M, LO, HI, M + 1, 0);
-    constexpr int NU = (M + 1) * (M + 2) / 2;
-    float2 h[NC];
-    int jcur = -1;
     float2 Y[NR][NP];
     static_for<0, NR>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -161,20 +176,12 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const do
         if constexpr (i >= 2 * M) {
             constexpr int r = i - 2 * M;  // output row x0 + r0 + r
             constexpr int c = r + M;      // its pair sums
-            const int j = index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
+            const int j = jrow[r];
             if (__builtin_amdgcn_ballot_w64(j != jcur) != 0) {
-                const int toff = j * (NU * 8);
-                static_for<0, M + 1>([&](auto AA) {
-                    constexpr int a = decltype(AA)::value;
-                    static_for<0, a + 1>([&](auto BB) {
-                        constexpr int b = decltype(BB)::value;
-                        if constexpr (in_set(a, LO, HI) || in_set(b, LO, HI))
-                            h[pass_slot(M, LO, HI, a, b)] = buf_load_c64(rt, toff + cidx(a, b) * 8);
-                    });
-                });
+                load_pass_taps<M, LO, HI>(h, rt, j);
                 jcur = j;
             }
-            float2 o = acc[r];
+            Acc3 o{acc[r].x, 0.0f, acc[r].y};
             static_for<0, M + 1>([&](auto AA) {
                 constexpr int a = decltype(AA)::value;
                 static_for<0, a + 1>([&](auto BB) {
@@ -203,23 +210,71 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const do
                             else
                                 sum = c_add(Y[c + a][b - LO], Y[c - a][b - LO]);
                         }
-                        o = c_fma(h[n], sum, o);
+                        o.re1 = fmaf(h[n].x, sum.x, o.re1);
+                        o.re2 = fmaf(h[n].y, sum.y, o.re2);
+                        o.im = fmaf(h[n].x, sum.y, o.im);
+                        o.im = fmaf(h[n].y, sum.x, o.im);
                     }
                 });
             });
+            float2 out = make_float2(o.re1 - o.re2, o.im);
             if constexpr (LAST) {
-                img[r] += (double)o.x;
-                buf_store_c64(rq, qbase + r * ny8, o);
+                img[r] += (double)out.x;
+                buf_store_c64(rq, qbase + r * ny8, out);
             } else {
                 // Pin the partial sum here: otherwise the compiler sinks this
                 // pass's arithmetic to its use in the next pass and keeps the
                 // whole pair-sum window of every row alive until then.
-                __asm__ volatile("" : "+v"(o.x), "+v"(o.y));
-                acc[r] = o;
+                __asm__ volatile("" : "+v"(out.x), "+v"(out.y));
+                acc[r] = out;
             }
         }
         __builtin_amdgcn_sched_barrier(0);
     });
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Stage the tile of one frequency plane into LDS by direct buffer-to-LDS
+// loads (no registers on the way): each wave copies its rows, a row being
+// the 2 (64 + 2M) dwords of columns y0 - M .. y0 + 63 + M, 64 dwords per
+// instruction.  Rows outside [0, nx) lie outside the buffer and arrive as
+// zeros; columns outside [0, ny) are cleared afterwards (fix_edges).
+template <int M>
+__device__ __forceinline__ void stage_rows(float2* Tb, __amdgpu_buffer_rsrc_t rp, int x0, int y0,
+                                           int ny, int wave, int lane)
+{
+    constexpr int W = kLanes3 + 2 * M;
+    constexpr int H = kTileX3 + 2 * M;
+    constexpr int HP = (H + kWaves3 - 1) / kWaves3 * kWaves3;
+    constexpr int DW = 2 * W;  // dwords per row
+#pragma unroll
+    for (int q = 0; q < HP / kWaves3; ++q) {
+        const int r = q * kWaves3 + wave;
+        const int row_off = ((x0 - M + r) * ny + (y0 - M)) * 8;
+#pragma unroll
+        for (int i = 0; i < (DW + 63) / 64; ++i) {
+            if (i * 64 + lane < DW)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rp, (lds_ptr_t)(reinterpret_cast<char*>(Tb + r * W) + i * 256), 4,
+                    row_off + (i * 64 + lane) * 4, 0, 0, 0);
+        }
+    }
+}
+
+// Zero the staged columns that lie outside [0, ny): [0, cl) and [ch, W).
+template <int M>
+__device__ __forceinline__ void fix_edges(float2* Tb, int cl, int ch)
+{
+    constexpr int W = kLanes3 + 2 * M;
+    constexpr int H = kTileX3 + 2 * M;
+    const int hi0 = ch > cl ? ch : cl;
+    const int nc = cl + (W > hi0 ? W - hi0 : 0);
+    for (int e = threadIdx.x; e < H * nc; e += kThreads3) {
+        const int r = e / nc, k = e % nc;
+        const int c = k < cl ? k : hi0 + (k - cl);
+        Tb[r * W + c] = make_float2(0.0f, 0.0f);
+    }
 }
 
 template <int M>
@@ -230,7 +285,9 @@ k_step3d(Step3dArgs A)
     constexpr int H = kTileX3 + 2 * M;       // LDS tile rows (with halo)
     constexpr int HP = (H + kWaves3 - 1) / kWaves3 * kWaves3;  // padded to whole wave rounds
     constexpr int SPLIT = M >= 3 ? (M + 1) / 2 : M + 1;  // planes of the first pass
-    __shared__ float2 T[HP * W];
+    constexpr int NC1 = pass_slot(M, 0, SPLIT, M + 1, 0);
+    constexpr int NC2 = pass_slot(M, SPLIT, M + 1, M + 1, 0);
+    __shared__ float2 T[2][HP * W];            // double-buffered frequency tiles
     __shared__ double S[kTileX3 * kLanes3];
 
     const int ntiles = A.tiles_x * A.tiles_y;
@@ -253,50 +310,67 @@ k_step3d(Step3dArgs A)
     for (int r = 0; r < kRows3; ++r) img[r] = 0.0;
     const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
         (void*)A.tab, 0, A.nk * ((M + 1) * (M + 2) / 2) * (int)sizeof(float2), kRawBufferWord3);
-
-    const int wbeg = g * A.wpg;
-    const int wend = wbeg + A.wpg < A.nw ? wbeg + A.wpg : A.nw;
-    // Columns this lane stages: y0 - M + lane and, for the first 2M lanes,
-    // the right halo 64 columns further; outside [0, ny) they stage zeros.
-    const int yc = y0 - M + lane, yc2 = yc + kLanes3;
-    const bool ym = yc >= 0 && yc < A.ny;
-    const bool yh = lane < 2 * M && yc2 < A.ny;
     const int ny8 = A.ny * 8;
     // Byte offset of this lane's first output within a plane.  Rows at or
     // past nx land past the plane's end by themselves; a column past ny is
     // moved out of range as a whole (stores out of range are dropped).
     const int qbase = y < A.ny ? (x0 + r0) * ny8 + y * 8 : 0x40000000;
-    for (int w = wbeg; w < wend; ++w) {
-        // Rows outside [0, nx) fall outside the buffer's range and load zeros.
-        const __amdgpu_buffer_rsrc_t rp =
-            __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)w * plane), 0,
-                                              (int)(plane * sizeof(float2)), kRawBufferWord3);
-        __syncthreads();  // the previous frequency's tile is no longer read
-#pragma unroll
-        for (int q = 0; q < HP / kWaves3; ++q) {
-            // rows H..HP-1 are padding: staged but never read
-            const int r = q * kWaves3 + wave;
-            const int xo = (x0 - M + r) * ny8;
-            const float2 v = buf_load_c64(rp, xo + yc * 8);
-            const float2 v2 = buf_load_c64(rp, xo + yc2 * 8);
-            T[r * W + lane] = ym ? v : make_float2(0.0f, 0.0f);
-            if (lane < 2 * M) T[r * W + kLanes3 + lane] = yh ? v2 : make_float2(0.0f, 0.0f);
-        }
-        __syncthreads();
+    // staged columns outside the volume: [0, cl) and [ch, W)
+    const int cl = M - y0 > 0 ? M - y0 : 0;
+    const int ch = A.ny - (y0 - M);
+    const bool edge = cl > 0 || ch < W;
+    const int pbytes = (int)(plane * sizeof(float2));
 
-        const double ar = A.omega[w] / A.dk;
-        const float2* Tw = T + r0 * W + lane + M;  // tile row of x0 + r0 - M, column y
+    const int wbeg = g * A.wpg;
+    const int wend = wbeg + A.wpg < A.nw ? wbeg + A.wpg : A.nw;
+    stage_rows<M>(T[0], __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)wbeg * plane), 0,
+                                                         pbytes, kRawBufferWord3),
+                  x0, y0, A.ny, wave, lane);
+    double om = A.omega[wbeg];  // frequency of the coming iteration, loaded one ahead
+    for (int w = wbeg; w < wend; ++w) {
+        const int cur = (w - wbeg) & 1;
+        float2* Tb = T[cur];
+        // This wave's copies into Tb are complete; after the barrier so are
+        // every wave's, and nobody reads the other buffer any more.
+        wait_vmem_all();
+        __syncthreads();
+        if (edge) {
+            fix_edges<M>(Tb, cl, ch);
+            __syncthreads();
+        }
+        const double ar = om / A.dk;
+        if (w + 1 < wend) om = A.omega[w + 1];
+        int jrow[kRows3];
+#pragma unroll
+        for (int r = 0; r < kRows3; ++r)
+            jrow[r] = index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
+        // First taps of the first pass, requested before the next tile's copy
+        // so that waiting for them does not wait for the copy (loads complete
+        // in order).
+        float2 h1[NC1];
+        int j1 = jrow[0];
+        load_pass_taps<M, 0, SPLIT>(h1, rt, j1);
+        __asm__ volatile("" ::: "memory");
+        if (w + 1 < wend)
+            stage_rows<M>(T[cur ^ 1],
+                          __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)(w + 1) * plane),
+                                                            0, pbytes, kRawBufferWord3),
+                          x0, y0, A.ny, wave, lane);
+
+        const float2* Tw = Tb + r0 * W + lane + M;  // tile row of x0 + r0 - M, column y
         const __amdgpu_buffer_rsrc_t rq =
-            __builtin_amdgcn_make_buffer_rsrc((void*)(A.out + (size_t)w * plane), 0,
-                                              (int)(plane * sizeof(float2)), kRawBufferWord3);
+            __builtin_amdgcn_make_buffer_rsrc((void*)(A.out + (size_t)w * plane), 0, pbytes,
+                                              kRawBufferWord3);
         float2 acc[kRows3];
 #pragma unroll
         for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
         if constexpr (SPLIT <= M) {
-            fir_pass<M, 0, SPLIT, false>(Tw, S, lane, r0, ar, A, rt, acc, img, rq, qbase, ny8);
-            fir_pass<M, SPLIT, M + 1, true>(Tw, S, lane, r0, ar, A, rt, acc, img, rq, qbase, ny8);
+            fir_pass<M, 0, SPLIT, false>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8);
+            float2 h2[NC2];
+            int j2 = -1;
+            fir_pass<M, SPLIT, M + 1, true>(Tw, jrow, h2, j2, rt, acc, img, rq, qbase, ny8);
         } else {
-            fir_pass<M, 0, M + 1, true>(Tw, S, lane, r0, ar, A, rt, acc, img, rq, qbase, ny8);
+            fir_pass<M, 0, M + 1, true>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8);
         }
     }
 

@@ -66,10 +66,14 @@ def _tol(desc, steps):
     return 8e-7 * (steps + 1) * nu
 
 
-@pytest.mark.parametrize("which", ["cfg5", "point", "small5"])
+@pytest.mark.parametrize("which", ["cfg5", "point", "small5", "grid64"])
 def test_design2d_matches_oracle(which, tables2d, cfg5_desc):
-    desc = {"cfg5": cfg5_desc, "point": synth.point_scatterer_3d().desc,
-            "small5": synth.random_volume(1, 4, 4, 2, 2, ntaps=5, nk=32).desc}[which]
+    if which == "grid64":  # largest design grid: more than 64 KB of LDS per workgroup
+        desc = dataclasses.replace(synth.random_volume(2, 4, 4, 2, 2, ntaps=11, nk=24).desc,
+                                   ngrid=64, ncheck=256)
+    else:
+        desc = {"cfg5": cfg5_desc, "point": synth.point_scatterer_3d().desc,
+                "small5": synth.random_volume(1, 4, 4, 2, 2, ntaps=5, nk=32).desc}[which]
     (ot, omg, ope, _), g = tables2d(desc)
     t64 = g["tab64"].cpu().numpy()
     err = np.abs(t64 - ot).max() / np.abs(ot).max()
