@@ -160,17 +160,33 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const in
     constexpr int NP = HI - LO;
     constexpr int NR = kRows3 + 2 * M;
     float2 Y[NR][NP];
-    static_for<0, NR>([&](auto I) {
+    // The LDS values of row i+1 are requested before row i's arithmetic, so
+    // their latency hides behind it (v[i & 1] holds row i: index 2q for
+    // column +b, 2q+1 for column -b of plane b = LO + q).
+    float2 v[2][2 * NP];
+    auto fetch = [&](auto I) {
         constexpr int i = decltype(I)::value;
         const float2* row = Tw + i * W;
         static_for<0, NP>([&](auto Q) {
-            constexpr int b = LO + decltype(Q)::value;
+            constexpr int q = decltype(Q)::value;
+            constexpr int b = LO + q;
+            v[i & 1][2 * q] = row[b];
+            if constexpr (b != 0) v[i & 1][2 * q + 1] = row[-b];
+        });
+    };
+    fetch(std::integral_constant<int, 0>{});
+    static_for<0, NR>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i + 1 < NR) fetch(std::integral_constant<int, i + 1>{});
+        static_for<0, NP>([&](auto Q) {
+            constexpr int q = decltype(Q)::value;
+            constexpr int b = LO + q;
             if constexpr (b == 0) {
-                Y[i][0] = row[0];
+                Y[i][0] = v[i & 1][0];
             } else {
-                Y[i][b - LO] = c_add(row[b], row[-b]);
+                Y[i][q] = c_add(v[i & 1][2 * q], v[i & 1][2 * q + 1]);
                 // Keep the pair sum (not its two operands) alive across rows.
-                __asm__ volatile("" : "+v"(Y[i][b - LO].x), "+v"(Y[i][b - LO].y));
+                __asm__ volatile("" : "+v"(Y[i][q].x), "+v"(Y[i][q].y));
             }
         });
         if constexpr (i >= 2 * M) {
@@ -248,17 +264,21 @@ __device__ __forceinline__ void stage_rows(float2* Tb, __amdgpu_buffer_rsrc_t rp
     constexpr int H = kTileX3 + 2 * M;
     constexpr int HP = (H + kWaves3 - 1) / kWaves3 * kWaves3;
     constexpr int DW = 2 * W;  // dwords per row
+    // wave, x0, y0 and ny are wave-uniform: row offsets and LDS destinations
+    // are scalar; one vector add per row, chunks of 64 dwords by the
+    // instruction's immediate offset, which applies to the global and the LDS
+    // address alike (so the LDS base stays at the row start).
+    const int lane4 = lane * 4;
 #pragma unroll
     for (int q = 0; q < HP / kWaves3; ++q) {
         const int r = q * kWaves3 + wave;
-        const int row_off = ((x0 - M + r) * ny + (y0 - M)) * 8;
-#pragma unroll
-        for (int i = 0; i < (DW + 63) / 64; ++i) {
+        const int voff = ((x0 - M + r) * ny + (y0 - M)) * 8 + lane4;
+        char* dst = reinterpret_cast<char*>(Tb + r * W);
+        static_for<0, (DW + 63) / 64>([&](auto I) {
+            constexpr int i = decltype(I)::value;
             if (i * 64 + lane < DW)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rp, (lds_ptr_t)(reinterpret_cast<char*>(Tb + r * W) + i * 256), 4,
-                    row_off + (i * 64 + lane) * 4, 0, 0, 0);
-        }
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rp, (lds_ptr_t)dst, 4, voff, 0, i * 256, 0);
+        });
     }
 }
 
@@ -294,7 +314,8 @@ k_step3d(Step3dArgs A)
     const int bid = logical_block();
     const int g = bid / ntiles, t = bid % ntiles;
     const int x0 = (t / A.tiles_y) * kTileX3, y0 = (t % A.tiles_y) * kLanes3;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const size_t plane = (size_t)A.nx * A.ny;
     const int y = y0 + lane;
     const int r0 = wave * kRows3;
