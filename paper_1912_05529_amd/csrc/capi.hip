@@ -200,7 +200,7 @@ bool sizes_ok(int nx, int nw) { return nx >= 1 && nx <= MIG_MAX_NX && nw >= 1 &&
 struct BatchPlan {
     size_t bytes = 0;
     struct Group {
-        int kind = 0, threads = 0, max_nx = 0, max_rows = 0, max_ldp = 0, nred = 0;
+        int kind = 0, threads = 0, max_nx = 0, max_rows = 0, max_ldp = 0, nred = 0, parts = 1;
         std::vector<SecDev> secs;
         std::vector<ItemDev> items;
         std::vector<TaskDev> tasks;
@@ -290,6 +290,7 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
         for (const SecDev& S : g.secs) total_blocks += blocks_of(S.nsteps);
         g.nred = reducer_count((int)g.items.size(), tn.nred);
         const int parts = parts_for(total_blocks, g.nred, g.max_nx);
+        g.parts = parts;
         for (int c = 0; c < blocks_of(g.max_rows); ++c)
             for (int si : order) {
                 if (c >= blocks_of(g.secs[si].nsteps)) continue;
@@ -344,7 +345,9 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
         a.nitems = (int)g.items.size();
         a.ntasks = (int)g.tasks.size();
         a.nred = g.nred < a.ntasks ? g.nred : a.ntasks;
-        a.parts = 1;
+        // a batch of one section derives its tasks from `parts` (task_of) with
+        // the same split as the task list built by the planner
+        a.parts = g.parts;
         a.nk = d->nk;
         a.M = M;
         a.dk = (d->kmax - d->kmin) / (double)(d->nk - 1);

@@ -66,6 +66,17 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b)
     return make_float2(a.x + b.x, a.y + b.y);
 }
 
+// Partial image rows are stored write-through (agent-scope relaxed atomic
+// stores): reducers on other XCDs read them after the block's release, and
+// the release then finds nothing of them left to write back from L2.
+__device__ __forceinline__ void store_partial2(float* p, float a, float b)
+{
+    const unsigned long long u =
+        (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int M>
 __device__ __forceinline__ void load_taps(float2 (&h)[M + 1], const float2* __restrict__ row)
 {
@@ -187,6 +198,7 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
     for (int i = q; i < a.ntasks; i += a.nred) {
         const TaskDev T = task_of(a, i);
         const SecDev S = sec_of(a, T.sec);
+        if (T.block * kPublish >= S.nsteps) continue;  // no such block (uniform)
         if (threadIdx.x == 0) {
             int v, last = -1;
             unsigned long long t0 = wall_clock64();
@@ -270,7 +282,7 @@ __device__ __forceinline__ void step_fast(const BatchArgs& a, const SecDev& S, f
     if (ROWS && k >= 1) {
         float* pr = L.live ? S.part + ((size_t)(k - 1) * S.nw + L.r) * S.ldp + L.x0
                            : a.trash + L.x0;
-        *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
+        store_partial2(pr, o0.x, o1.x);
     }
     // sn = slowness of step k+1, flagged where it differs from step k-1 (the
     // step the other set was last loaded for)
@@ -352,7 +364,7 @@ __global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
     if (ROWS) {
         float* pr = L.live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + L.r) * S.ldp + L.x0
                            : a.trash + L.x0;
-        *reinterpret_cast<float2*>(pr) = make_float2(o0.x, o1.x);
+        store_partial2(pr, o0.x, o1.x);
         __syncthreads();
         publish_block(S, (S.nsteps - 1) / kPublish);
     }
@@ -417,7 +429,8 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
         wait_vmem_all();
         if (ROWS && k >= 1) {
             float* pr = live ? S.part + ((size_t)(k - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
-            *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
+            store_partial2(pr, o[0].x, o[1].x);
+            store_partial2(pr + 2, o[2].x, o[3].x);
         }
         // slowness of step k+1 (flagged where it differs from step k), used
         // after the FIR to refill taps
@@ -442,7 +455,8 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
     }
     if (ROWS) {
         float* pr = live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
-        *reinterpret_cast<float4*>(pr) = make_float4(o[0].x, o[1].x, o[2].x, o[3].x);
+        store_partial2(pr, o[0].x, o[1].x);
+        store_partial2(pr + 2, o[2].x, o[3].x);
         __syncthreads();
         publish_block(S, (S.nsteps - 1) / kPublish);
     }

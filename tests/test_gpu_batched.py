@@ -101,3 +101,21 @@ def test_autotuner_picks_a_measured_candidate(mixed):
     best, table = tuner.autotune(batch, tab["tab32"], desc, reps=1)
     assert best in [row["tune"] for row in table]
     assert all(row["ms"] > 0 for row in table)
+
+
+@pytest.mark.parametrize("nx,nz,nw,reducers", [(1024, 40, 8, 24), (1024, 40, 8, 48),
+                                               (777, 70, 5, 32), (300, 18, 3, 64),
+                                               (1500, 33, 4, 40)])
+def test_batch_of_one_section_splits_blocks_like_the_planner(nx, nz, nw, reducers):
+    """A batch of one section derives its reducer tasks from the split count;
+    with enough reducers each published block is split along x, and the
+    result must still be the per-section migration, bit for bit."""
+    s = synth.random_case(4000 + nx, nx, nz, nw, ntaps=35, nk=256)
+    tab = mig.design_table(s.desc, dev())
+    t = upload(s)
+    ref = mig.migrate(t["data"], t["vel"], t["omega"], tab["tab32"], s.desc)
+    b = [dict(t)]
+    mig.migrate_batched(b, tab["tab32"], s.desc, tune={"reducers": reducers})
+    torch.cuda.synchronize()
+    assert torch.isfinite(b[0]["image"]).all()
+    assert torch.equal(b[0]["image"], ref)
