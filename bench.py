@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (no batched / adjoint / 3-D extras)")
     ap.add_argument("--traffic", default=None,
-                    help="JSON file with rocprofv3-derived HBM bytes per launch")
+                    help="JSON file with rocprofv3-derived HBM bytes per launch "
+                         "(default profiles/traffic.json)")
     ap.add_argument("--profile", choices=["plain", "batched", "adjoint", "volume3d"],
                     default=None,
                     help="short run of one part for profilers: warmup + steps, no oracle, "
@@ -63,6 +64,25 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     return ap.parse_args()
+
+
+def profiled_traffic(args, key):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE and WRITE_SIZE
+    scaled by a copy calibration; see profiles/), or None when the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    path = args.traffic or os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        e = json.load(f).get(key)
+    if not e:
+        return None
+    h = hashlib.sha1()
+    for src in e["source"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return e["bytes_per_launch"] if h.hexdigest() == e["source_sha1"] else None
 
 
 class Timer:
@@ -161,10 +181,7 @@ def headline(torch, mig, synth, dev, args):
     flop_alg = outputs * (8 * (M + 1) + 2 * M)
     value = tap_macs / (ms_step * 1e-3) / 1e9
     achieved = flop_alg / (ms_kernel * 1e-3) / 1e12
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = profiled_traffic(args, "k_extrap_fast<17,true> config2")
     res = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -399,6 +416,7 @@ def volume3d(torch, mig, synth, dev, args, profile=False):
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "flop_per_output": flop_out,
+            "traffic": profiled_traffic(args, "k_step3d<5> config5"),
         },
     }
     if not args.no_cpu_baseline:

@@ -8,8 +8,10 @@
 //     (E_k^H q)[x] = sum_{n=-M..M} conj(h_{j(x+n,k)}[|n|]) q[x+n]:
 // every point x+n contributes through the filter of that point.  A workgroup
 // owns one frequency for all depths (walking them backwards); per step it
-// forms g_m[y] = conj(h_{j(y)}[m]) q[y] for its points in LDS, a chunk of m
-// at a time, and gathers out[x] = g_0[x] + sum_m (g_m[x-m] + g_m[x+m]).
+// forms g_m[y] = conj(h_{j(y)}[m]) q[y] for its points in LDS and gathers
+// out[x] = g_0[x] + sum_m (g_m[x-m] + g_m[x+m]).  The register-tap kernel
+// (nx <= 1024, N <= 35) does all taps in one LDS pass; the general kernel
+// handles any size a chunk of taps at a time.
 #include "common.hpp"
 
 namespace mig {
@@ -72,7 +74,142 @@ __global__ void __launch_bounds__(512) k_demigrate(AdjArgs a)
     for (int x = threadIdx.x; x < nx; x += blockDim.x) a.out[(size_t)x * nw + r] = Q[x];
 }
 
+// Register-tap form (nx <= 2 * kAdjThreads, M <= kAdjMaxM): each thread owns
+// two adjacent points y, y+1 of the frequency, keeps their Q values and their
+// (M+1) taps in registers (refilled only where the slowness changes going up
+// a step), writes the products conj(h_y[m]) q[y] of every tap m to LDS in one
+// pass, and after one barrier gathers its two outputs from them.  The plane Q
+// never leaves registers; two barriers per depth step.
+constexpr int kAdjThreads = 512;
+constexpr int kAdjMaxM = 17;
+
+template <int M>
+__device__ __forceinline__ void load_taps_adj(float2 (&h)[M + 1], const float2* __restrict__ row)
+{
+#pragma unroll
+    for (int m = 0; m <= M; ++m) h[m] = row[m];
+}
+
+template <int M>
+__global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
+{
+    extern __shared__ float4 smem4[];
+    float2* G = reinterpret_cast<float2*>(smem4);  // [M+1][nx + 2M], zero outside [M, M + nx)
+    const int nx = a.nx, LG = nx + 2 * M, r = blockIdx.x;
+    const double ar = a.omega[r] / a.dk;
+    const int y0 = 2 * threadIdx.x;
+    const bool live0 = y0 < nx, live1 = y0 + 1 < nx;
+
+    for (int i = threadIdx.x; i < (M + 1) * LG; i += blockDim.x) G[i] = make_float2(0.0f, 0.0f);
+    float2 q0 = make_float2(live0 ? (float)a.image[(size_t)(a.nz - 1) * nx + y0] : 0.0f, 0.0f);
+    float2 q1 = make_float2(live1 ? (float)a.image[(size_t)(a.nz - 1) * nx + y0 + 1] : 0.0f, 0.0f);
+    float2 h0[M + 1], h1[M + 1];
+    if (a.nz > 1) {
+        const double* srow = a.slow + (size_t)(a.nz - 2) * a.ldp;
+        load_taps_adj<M>(h0, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
+                                                               slowness_value(srow[live0 ? y0 : 0])) * (M + 1));
+        load_taps_adj<M>(h1, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
+                                                               slowness_value(srow[live1 ? y0 + 1 : 0])) * (M + 1));
+    }
+    __syncthreads();
+
+    for (int k = a.nz - 2; k >= 0; --k) {
+        // slowness of this step's row (its flag: differs from the row above)
+        // and of the row above, for the refill at the end of the step
+        const double* srow = a.slow + (size_t)k * a.ldp;
+        const double fk0 = srow[live0 ? y0 : 0], fk1 = srow[live1 ? y0 + 1 : 0];
+        double su0 = 0.0, su1 = 0.0;
+        if (k >= 1) {
+            su0 = a.slow[(size_t)(k - 1) * a.ldp + (live0 ? y0 : 0)];
+            su1 = a.slow[(size_t)(k - 1) * a.ldp + (live1 ? y0 + 1 : 0)];
+        }
+        const double i0 = live0 ? a.image[(size_t)k * nx + y0] : 0.0;
+        const double i1 = live1 ? a.image[(size_t)k * nx + y0 + 1] : 0.0;
+        if (live0) {
+            // q1 = 0 when y0 + 1 is past the end: the store keeps that border zero
+            float2* g = G + M + y0;
+#pragma unroll
+            for (int m = 0; m <= M; ++m) {
+                g[(size_t)m * LG] = cmul_conj(h0[m], q0);
+                g[(size_t)m * LG + 1] = cmul_conj(h1[m], q1);
+            }
+        }
+        __syncthreads();
+        float2 a0 = make_float2((float)i0, 0.0f), a1 = make_float2((float)i1, 0.0f);
+        if (live0) {
+            const float2* g = G + M + y0;
+            a0.x += g[0].x;
+            a0.y += g[0].y;
+#pragma unroll
+            for (int m = 1; m <= M; ++m) {
+                const float2* gm = g + (size_t)m * LG;
+                a0.x += gm[-m].x + gm[m].x;
+                a0.y += gm[-m].y + gm[m].y;
+            }
+        }
+        if (live1) {
+            const float2* g = G + M + y0 + 1;
+            a1.x += g[0].x;
+            a1.y += g[0].y;
+#pragma unroll
+            for (int m = 1; m <= M; ++m) {
+                const float2* gm = g + (size_t)m * LG;
+                a1.x += gm[-m].x + gm[m].x;
+                a1.y += gm[-m].y + gm[m].y;
+            }
+        }
+        __syncthreads();
+        q0 = live0 ? a0 : make_float2(0.0f, 0.0f);
+        q1 = live1 ? a1 : make_float2(0.0f, 0.0f);
+        if (k >= 1) {
+            if (slowness_changed(fk0))
+                load_taps_adj<M>(h0, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
+                                                                       slowness_value(su0)) * (M + 1));
+            if (slowness_changed(fk1))
+                load_taps_adj<M>(h1, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
+                                                                       slowness_value(su1)) * (M + 1));
+        }
+    }
+    if (live0) a.out[(size_t)y0 * a.nw + r] = q0;
+    if (live1) a.out[(size_t)(y0 + 1) * a.nw + r] = q1;
+}
+
+template <int M>
+int launch_reg(const AdjArgs& a, size_t lds, hipStream_t s)
+{
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_demigrate_reg<M>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return MIG_E_DEVICE;
+    const int threads = ((a.nx + 1) / 2 + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_demigrate_reg<M>, dim3(a.nw), dim3(threads), lds, s, a);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
 }  // namespace
+
+bool adjoint_uses_registers(int nx, int M, size_t lds_limit)
+{
+    // M >= 1: the pair store of the last point of an odd nx lands on the
+    // right border, which then exists
+    return nx <= 2 * kAdjThreads && M >= 1 && M <= kAdjMaxM &&
+           (size_t)(M + 1) * (nx + 2 * M) * sizeof(float2) <= lds_limit;
+}
+
+int launch_demigrate_reg(const AdjArgs& a, hipStream_t s)
+{
+    const size_t lds = (size_t)(a.M + 1) * (a.nx + 2 * a.M) * sizeof(float2);
+    switch (a.M) {
+#define MIG_ADJ_CASE(m) \
+    case m: return launch_reg<m>(a, lds, s);
+    MIG_ADJ_CASE(1) MIG_ADJ_CASE(2) MIG_ADJ_CASE(3) MIG_ADJ_CASE(4)
+    MIG_ADJ_CASE(5) MIG_ADJ_CASE(6) MIG_ADJ_CASE(7) MIG_ADJ_CASE(8) MIG_ADJ_CASE(9)
+    MIG_ADJ_CASE(10) MIG_ADJ_CASE(11) MIG_ADJ_CASE(12) MIG_ADJ_CASE(13) MIG_ADJ_CASE(14)
+    MIG_ADJ_CASE(15) MIG_ADJ_CASE(16) MIG_ADJ_CASE(17)
+#undef MIG_ADJ_CASE
+    default: return MIG_E_ARG;
+    }
+}
 
 int adjoint_chunk(int nx, int M, size_t lds_limit)
 {

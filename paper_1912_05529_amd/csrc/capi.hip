@@ -555,8 +555,9 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
         lds_max = 65536;
     const int M = (d->ntaps - 1) / 2;
     AdjArgs a = {};
+    const bool reg = adjoint_uses_registers(nx, M, (size_t)lds_max);
     a.chunk = adjoint_chunk(nx, M, (size_t)lds_max);
-    if (a.chunk < 1) return MIG_E_ARG;
+    if (!reg && a.chunk < 1) return MIG_E_ARG;
     hipStream_t s = as_stream(stream);
     a.image = image;
     a.slow = static_cast<const double*>(ws);
@@ -579,10 +580,13 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
         sa.one.nx = nx;
         sa.one.nsteps = nz - 1;
         sa.one.ldp = a.ldp;
-        int rc = launch_slowness(sa, nz - 1, a.ldp, 0, s);
+        // change flags against the previous row: walking depth upward, the
+        // register-tap kernel refills a point's taps where its row differs
+        // from the row above
+        int rc = launch_slowness(sa, nz - 1, a.ldp, 1, s);
         if (rc != MIG_OK) return rc;
     }
-    return launch_demigrate(a, s);
+    return reg ? launch_demigrate_reg(a, s) : launch_demigrate(a, s);
 }
 
 MIG_API size_t mig_transform_workspace_size(int32_t nt, int32_t nw)

@@ -150,6 +150,9 @@ int launch_zero(int* p, int n, hipStream_t s);
 // Taps per LDS pass of the demigration kernel for an LDS budget (0 = too big).
 int adjoint_chunk(int nx, int M, size_t lds_limit);
 int launch_demigrate(const AdjArgs& a, hipStream_t s);
+// Register-tap adjoint kernel: usable for these sizes within an LDS budget?
+bool adjoint_uses_registers(int nx, int M, size_t lds_limit);
+int launch_demigrate_reg(const AdjArgs& a, hipStream_t s);
 // Transform along t: builds the FP32 DFT matrix B [nt][2 nw] and computes the
 // plane out [nx][nw] = section [nx][nt] . B on the matrix cores.
 int launch_transform(const float* section, int nx, int nt, double dt, const double* omega,
