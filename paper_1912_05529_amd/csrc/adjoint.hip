@@ -113,18 +113,19 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
     }
     __syncthreads();
 
-    for (int k = a.nz - 2; k >= 0; --k) {
-        // slowness of this step's row (its flag: differs from the row above)
-        // and of the row above, for the refill at the end of the step
-        const double* srow = a.slow + (size_t)k * a.ldp;
-        const double fk0 = srow[live0 ? y0 : 0], fk1 = srow[live1 ? y0 + 1 : 0];
-        double su0 = 0.0, su1 = 0.0;
-        if (k >= 1) {
-            su0 = a.slow[(size_t)(k - 1) * a.ldp + (live0 ? y0 : 0)];
-            su1 = a.slow[(size_t)(k - 1) * a.ldp + (live1 ? y0 + 1 : 0)];
-        }
-        const double i0 = live0 ? a.image[(size_t)k * nx + y0] : 0.0;
-        const double i1 = live1 ? a.image[(size_t)k * nx + y0 + 1] : 0.0;
+    // Values for the coming step k, loaded one step ahead: the flag of row k
+    // (differs from row k-1), the slowness of row k-1 (taps of the next
+    // step) and the image row k.
+    const int c0 = live0 ? y0 : 0, c1 = live1 ? y0 + 1 : 0;
+    auto slow_at = [&](int row, int c) { return row >= 0 ? a.slow[(size_t)row * a.ldp + c] : 0.0; };
+    auto img_at = [&](int row, int c, bool live) {
+        return live && row >= 0 ? a.image[(size_t)row * nx + c] : 0.0;
+    };
+    int k = a.nz - 2;
+    double fk0 = slow_at(k, c0), fk1 = slow_at(k, c1);
+    double su0 = slow_at(k - 1, c0), su1 = slow_at(k - 1, c1);
+    double i0 = img_at(k, c0, live0), i1 = img_at(k, c1, live1);
+    for (; k >= 0; --k) {
         if (live0) {
             // q1 = 0 when y0 + 1 is past the end: the store keeps that border zero
             float2* g = G + M + y0;
@@ -134,33 +135,9 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
                 g[(size_t)m * LG + 1] = cmul_conj(h1[m], q1);
             }
         }
-        __syncthreads();
-        float2 a0 = make_float2((float)i0, 0.0f), a1 = make_float2((float)i1, 0.0f);
-        if (live0) {
-            const float2* g = G + M + y0;
-            a0.x += g[0].x;
-            a0.y += g[0].y;
-#pragma unroll
-            for (int m = 1; m <= M; ++m) {
-                const float2* gm = g + (size_t)m * LG;
-                a0.x += gm[-m].x + gm[m].x;
-                a0.y += gm[-m].y + gm[m].y;
-            }
-        }
-        if (live1) {
-            const float2* g = G + M + y0 + 1;
-            a1.x += g[0].x;
-            a1.y += g[0].y;
-#pragma unroll
-            for (int m = 1; m <= M; ++m) {
-                const float2* gm = g + (size_t)m * LG;
-                a1.x += gm[-m].x + gm[m].x;
-                a1.y += gm[-m].y + gm[m].y;
-            }
-        }
-        __syncthreads();
-        q0 = live0 ? a0 : make_float2(0.0f, 0.0f);
-        q1 = live1 ? a1 : make_float2(0.0f, 0.0f);
+        // The taps are free now: refill them for step k-1 where the row
+        // changes, and prefetch the next step's slowness and image values, so
+        // the loads overlap the barrier and the gather.
         if (k >= 1) {
             if (slowness_changed(fk0))
                 load_taps_adj<M>(h0, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
@@ -169,6 +146,46 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
                 load_taps_adj<M>(h1, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
                                                                        slowness_value(su1)) * (M + 1));
         }
+        const double ci0 = i0, ci1 = i1;
+        fk0 = slow_at(k - 1, c0);
+        fk1 = slow_at(k - 1, c1);
+        su0 = slow_at(k - 2, c0);
+        su1 = slow_at(k - 2, c1);
+        i0 = img_at(k - 1, c0, live0);
+        i1 = img_at(k - 1, c1, live1);
+        __syncthreads();
+        // Two partial sums per output (taps m odd / m even) halve the chain of
+        // dependent additions.
+        float2 a0 = make_float2((float)ci0, 0.0f), a1 = make_float2((float)ci1, 0.0f);
+        if (live0) {
+            const float2* g = G + M + y0;
+            float2 e = g[0], o = make_float2(0.0f, 0.0f);
+#pragma unroll
+            for (int m = 1; m <= M; ++m) {
+                const float2* gm = g + (size_t)m * LG;
+                float2& t = (m & 1) ? o : e;
+                t.x += gm[-m].x + gm[m].x;
+                t.y += gm[-m].y + gm[m].y;
+            }
+            a0.x += e.x + o.x;
+            a0.y += e.y + o.y;
+        }
+        if (live1) {
+            const float2* g = G + M + y0 + 1;
+            float2 e = g[0], o = make_float2(0.0f, 0.0f);
+#pragma unroll
+            for (int m = 1; m <= M; ++m) {
+                const float2* gm = g + (size_t)m * LG;
+                float2& t = (m & 1) ? o : e;
+                t.x += gm[-m].x + gm[m].x;
+                t.y += gm[-m].y + gm[m].y;
+            }
+            a1.x += e.x + o.x;
+            a1.y += e.y + o.y;
+        }
+        __syncthreads();
+        q0 = live0 ? a0 : make_float2(0.0f, 0.0f);
+        q1 = live1 ? a1 : make_float2(0.0f, 0.0f);
     }
     if (live0) a.out[(size_t)y0 * a.nw + r] = q0;
     if (live1) a.out[(size_t)(y0 + 1) * a.nw + r] = q1;

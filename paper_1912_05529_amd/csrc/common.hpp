@@ -12,7 +12,7 @@ namespace mig {
 constexpr double kPi = 3.14159265358979323846;
 
 // Frequency workgroups publish their partial rows every kPublish depth steps.
-constexpr int kPublish = 16;
+constexpr int kPublish = 32;
 // Reducers poll a block counter with this s_sleep argument (x 64 cycles).
 constexpr int kPollSleep = 127;
 // Reducers give up (and write NaN rows) after this long without progress.
