@@ -168,6 +168,11 @@ def headline(torch, mig, synth, dev, args):
           file=sys.stderr, flush=True)
     ref_img = mig.migrate(data, vel, omega, tab["tab32"], desc, ws=ws)
     assert torch.equal(ref_img, img), "staged step differs from mig_migrate"
+    # the extrapolation alone (image rows off), reported beside the step
+    plane = torch.empty_like(data)
+    ms_rows_off = timed(torch, lambda: mig.extrapolate(data, vel, omega, tab["tab32"], desc,
+                                                       nz - 1, rows=False, out=plane, ws=ws),
+                        args.steps, warmup=args.warmup)
     if args.calib_copy:
         # plain copy kernel of known size, for scaling HBM byte counters
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
@@ -204,6 +209,11 @@ def headline(torch, mig, synth, dev, args):
         },
         "design_ms": round(design_ms, 3),
         "gen_s": round(gen_s, 2),
+        "extrapolate_rows_off": {
+            "ms": round(ms_rows_off, 4),
+            "tflops_algorithmic": round(flop_alg / (ms_rows_off * 1e-3) / 1e12, 3),
+            "frac_of_peak": round(flop_alg / (ms_rows_off * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+        },
         "roofline": {
             "bound": "alu",
             "kernel": "depth-stepping launch: register-tap kernel, all %d depth steps, fused "

@@ -315,6 +315,8 @@ MIG_API int mig_kernel_kind(int32_t nx, int32_t ntaps);
 #define MIG_MAX_NGRID_2D 64     /* design grid points per axis                */
 #define MIG_MAX_NCHECK_2D 4096  /* check grid points per axis                 */
 #define MIG_MAX_NXY 65536       /* lateral points per axis of a volume        */
+#define MIG_MAX_PLANE_3D 134217728 /* nx * ny per volume (2^27: one frequency
+                                      plane of complex64 within 1 GiB)        */
 
 MIG_API size_t mig_design2d_workspace_size(const mig_table_desc* d);
 MIG_API int mig_design_table_2d(const mig_table_desc* d, mig_c128* tab64,

@@ -632,8 +632,10 @@ bool design2d_desc_valid(const mig_table_desc* d)
 
 bool sizes3d_ok(int32_t nx, int32_t ny, int32_t nw, int32_t nz)
 {
+    // the depth-step kernel addresses one frequency plane with 32-bit offsets
     return nx >= 1 && nx <= MIG_MAX_NXY && ny >= 1 && ny <= MIG_MAX_NXY && nw >= 1 &&
-           nw <= MIG_MAX_NW && nz >= 1;
+           nw <= MIG_MAX_NW && nz >= 1 &&
+           (unsigned long long)nx * (unsigned long long)ny <= MIG_MAX_PLANE_3D;
 }
 
 // Frequencies per workgroup group: `want` if given, else enough groups that

@@ -65,8 +65,22 @@ __device__ void wls_solve(const double* __restrict__ A, const double* w,
             int p = 0;
             while ((p + 1) * (p + 2) / 2 <= task) ++p;
             int q = task - p * (p + 1) / 2;
+            // Loads of 8 grid points are issued ahead of their (sequential,
+            // grid-ordered) accumulation, which keeps the oracle's order.
             double s = 0.0;
-            for (int i = 0; i < L; ++i) {
+            int i = 0;
+            for (; i + 8 <= L; i += 8) {
+                double wv[8], ap[8], aq[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    wv[u] = w[i + u];
+                    ap[u] = A[(size_t)(i + u) * K + p];
+                    aq[u] = A[(size_t)(i + u) * K + q];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += wv[u] * ap[u] * aq[u];
+            }
+            for (; i < L; ++i) {
                 const double* a = A + (size_t)i * K;
                 s += w[i] * a[p] * a[q];
             }
@@ -75,7 +89,24 @@ __device__ void wls_solve(const double* __restrict__ A, const double* w,
         } else {
             int p = task - npair;
             double sr = 0.0, si = 0.0;
-            for (int i = 0; i < L; ++i) {
+            int i = 0;
+            for (; i + 8 <= L; i += 8) {
+                double wv[8], ap[8], dr[8], di[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    wv[u] = w[i + u];
+                    ap[u] = A[(size_t)(i + u) * K + p];
+                    dr[u] = Dr[i + u];
+                    di[u] = Di[i + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double wa = wv[u] * ap[u];
+                    sr += wa * dr[u];
+                    si += wa * di[u];
+                }
+            }
+            for (; i < L; ++i) {
                 double wa = w[i] * A[(size_t)i * K + p];
                 sr += wa * Dr[i];
                 si += wa * Di[i];

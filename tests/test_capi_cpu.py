@@ -116,6 +116,8 @@ def test_3d_host_checks_and_workspace_sizes(L):
         assert mig.migrate3d_workspace_size(nx, ny, nw, 5, wpg) == (
             2 * al(nx * ny * nw * 8) + 2 * al(ng * nx * ny * 8))
     assert mig.migrate3d_workspace_size(0, 8, 2, 3) == 0
+    assert mig.migrate3d_workspace_size(16384, 8193, 1, 2) == 0      # plane over 2^27 points
+    assert mig.migrate3d_workspace_size(16384, 8192, 1, 2) > 0
     assert mig.migrate3d_workspace_size(8, 8, 2, 0) == 0
     assert mig.omegas_per_group_3d(8, 8, 2, -1) == -1
     cd = mig.cdesc(d2)
