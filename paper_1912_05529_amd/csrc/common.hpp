@@ -74,6 +74,31 @@ struct AdjArgs {
     double dk, b;
 };
 
+// A pointer that the compiler cannot see to be global (one read from a struct
+// of arguments) makes flat instructions, which also count against the LDS wait
+// counter: a barrier's LDS wait would then wait for them too.  Casting to the
+// global address space makes them global instructions.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// Loads of the HIP vector structs through a global pointer, as native vectors.
+__device__ __forceinline__ float2 load_global(const float2* p)
+{
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = *as_global(reinterpret_cast<const v2f*>(p));
+    return make_float2(v.x, v.y);
+}
+
+__device__ __forceinline__ double2 load_global(const double2* p)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    const v2d v = *as_global(reinterpret_cast<const v2d*>(p));
+    return make_double2(v.x, v.y);
+}
+
 // Slowness used by the table look-up: 1/v as an IEEE double division, or NaN
 // when v is not > 0 (which selects entry 0).
 __device__ __forceinline__ double slowness_of(float v)

@@ -73,7 +73,7 @@ __device__ __forceinline__ void store_partial2(float* p, float a, float b)
 {
     const unsigned long long u =
         (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED,
+    __hip_atomic_store(as_global(reinterpret_cast<unsigned long long*>(p)), u, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -179,12 +179,15 @@ __global__ void k_slowness(BatchArgs a, int dist)
 }
 
 // Thread 0 of a frequency workgroup, after a barrier that follows the stores of
-// the partial rows of block c: release them at agent scope and count.
+// the partial rows of block c: release them at agent scope and count.  Every
+// wave waits for its own stores to complete before that barrier
+// (wait_vmem_all): the release's wait covers only the stores of thread 0's
+// wave.
 __device__ __forceinline__ void publish_block(const SecDev& S, int c)
 {
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(S.cnt + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(as_global(S.cnt + c), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -202,7 +205,7 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
         if (threadIdx.x == 0) {
             int v, last = -1;
             unsigned long long t0 = wall_clock64();
-            while ((v = __hip_atomic_load(S.cnt + T.block, __ATOMIC_RELAXED,
+            while ((v = __hip_atomic_load(as_global(S.cnt + T.block), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT)) < S.nprod) {
                 unsigned long long now = wall_clock64();
                 if (v != last) {
@@ -227,14 +230,14 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
             const int st = s0 + it / npair;
             const int x0 = T.x0 + 2 * (it % npair);
             const float* p = S.part + (size_t)st * S.nw * S.ldp;
-            double* row = S.rows + (size_t)st * S.nx;
+            __attribute__((address_space(1))) double* row = as_global(S.rows + (size_t)st * S.nx);
             double a0 = 0.0, a1 = 0.0;
             int r = 0;
             for (; r + 8 <= S.nw; r += 8) {
                 float2 v[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    v[j] = *reinterpret_cast<const float2*>(p + (size_t)(r + j) * S.ldp + x0);
+                    v[j] = load_global(reinterpret_cast<const float2*>(p + (size_t)(r + j) * S.ldp + x0));
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     a0 += (double)v[j].x;
@@ -242,7 +245,7 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
                 }
             }
             for (; r < S.nw; ++r) {
-                float2 v = *reinterpret_cast<const float2*>(p + (size_t)r * S.ldp + x0);
+                float2 v = load_global(reinterpret_cast<const float2*>(p + (size_t)r * S.ldp + x0));
                 a0 += (double)v.x;
                 a1 += (double)v.y;
             }
@@ -295,12 +298,13 @@ __device__ __forceinline__ void step_fast(const BatchArgs& a, const SecDev& S, f
                                                                   slowness_value(sn.y)) * (M + 1));
     }
     const int kp = k + 2 < S.nsteps ? k + 2 : S.nsteps - 1;
-    const double2 p = *reinterpret_cast<const double2*>(S.slow + (size_t)kp * S.ldp + L.x0);
+    const double2 p = load_global(reinterpret_cast<const double2*>(S.slow + (size_t)kp * S.ldp + L.x0));
     fir2<M>(sm + (k & 1) * L.LB + 2 * L.t, hc[0], hc[1], o0, o1);
     float2* dst = sm + ((k + 1) & 1) * L.LB + M + L.x0;
     if (L.ok0) dst[0] = o0;
     if (L.ok1) dst[1] = o1;
     sn = p;
+    if (ROWS && k >= 1 && k % kPublish == 0) wait_vmem_all();
     __syncthreads();
     // the partial row of step k-1 is now stored by every thread
     if (ROWS && k >= 1 && k % kPublish == 0) publish_block(S, (k - 1) / kPublish);
@@ -365,6 +369,7 @@ __global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
         float* pr = L.live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + L.r) * S.ldp + L.x0
                            : a.trash + L.x0;
         store_partial2(pr, o0.x, o1.x);
+        wait_vmem_all();
         __syncthreads();
         publish_block(S, (S.nsteps - 1) / kPublish);
     }
@@ -436,7 +441,7 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
         // after the FIR to refill taps
         const int kp = k + 1 < S.nsteps ? k + 1 : S.nsteps - 1;
         const double2* sp = reinterpret_cast<const double2*>(S.slow + (size_t)kp * S.ldp + x0);
-        const double2 p01 = sp[0], p23 = sp[1];
+        const double2 p01 = load_global(sp), p23 = load_global(sp + 1);
         fir4<M>(sm + (k & 1) * LB + x0, h, o);
         float2* dst = sm + ((k + 1) & 1) * LB + M + x0;
 #pragma unroll
@@ -450,6 +455,7 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
                     load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
                                                                          slowness_value(sn[q])) * (M + 1));
         }
+        if (ROWS && k >= 1 && k % kPublish == 0) wait_vmem_all();
         __syncthreads();
         if (ROWS && k >= 1 && k % kPublish == 0) publish_block(S, (k - 1) / kPublish);
     }
@@ -457,6 +463,7 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
         float* pr = live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
         store_partial2(pr, o[0].x, o[1].x);
         store_partial2(pr + 2, o[2].x, o[3].x);
+        wait_vmem_all();
         __syncthreads();
         publish_block(S, (S.nsteps - 1) / kPublish);
     }
@@ -492,17 +499,18 @@ __global__ void __launch_bounds__(256) k_extrap_general(BatchArgs a)
     for (int k = 0; k < S.nsteps; ++k) {
         const float2* src = sm + (k & 1) * LB + M;
         float2* dst = sm + ((k + 1) & 1) * LB + M;
-        const double* sr = S.slow + (size_t)k * S.ldp;
+        const auto* sr = as_global(S.slow + (size_t)k * S.ldp);
         for (int x = threadIdx.x; x < nx; x += blockDim.x) {
             const float2* h = a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, slowness_value(sr[x])) * (M + 1);
             float2 acc = cmulf(h[0], src[x]);
             for (int n = 1; n <= M; ++n) acc = cfmaf(h[n], cadd(src[x - n], src[x + n]), acc);
             dst[x] = acc;
-            if (rows_on && live) S.part[((size_t)k * S.nw + r) * S.ldp + x] = acc.x;
+            if (rows_on && live) *as_global(S.part + ((size_t)k * S.nw + r) * S.ldp + x) = acc.x;
         }
+        const bool publish = rows_on && ((k + 1) % kPublish == 0 || k + 1 == S.nsteps);
+        if (publish) wait_vmem_all();
         __syncthreads();
-        if (rows_on && ((k + 1) % kPublish == 0 || k + 1 == S.nsteps))
-            publish_block(S, k / kPublish);
+        if (publish) publish_block(S, k / kPublish);
     }
     if (S.wout && live) {
         const float2* src = sm + (S.nsteps & 1) * LB + M;
