@@ -168,10 +168,16 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
         a.one.vel = vel + (size_t)c0 * nx;
         a.one.nsteps = cs;
         a.one.rows = rows ? rows + (size_t)c0 * nx : nullptr;
-        if (rows) {
+        // Reducer workgroups form the rows of every published block but the
+        // last, overlapped with the depth stepping; the last block, which
+        // nothing is left to overlap with, is reduced after the launch by the
+        // whole GPU (launch_rows).
+        const int nb = blocks_of(cs);
+        a.rows = rows ? 1 : 0;
+        if (rows && nb > 1) {
             const int nred = reducer_count(nitems, tn.nred);
-            a.parts = parts_for(blocks_of(cs), nred, nx);
-            a.ntasks = blocks_of(cs) * a.parts;
+            a.parts = parts_for(nb - 1, nred, nx);
+            a.ntasks = (nb - 1) * a.parts;
             a.nred = nred < a.ntasks ? nred : a.ntasks;
         } else {
             a.parts = 1;
@@ -184,6 +190,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
             if (kind == 0) rc = launch_general(a, nx, s);
             else rc = launch_extrap(a, kind, G * threads_per_omega(kind, nx), s);
         }
+        if (rc == MIG_OK && rows) rc = launch_rows(part, a.one.rows, (nb - 1) * kPublish, cs, nx, nw, ldp, s);
         if (rc != MIG_OK) return rc;
         cur = scratch;
     }
@@ -345,6 +352,7 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
         a.nitems = (int)g.items.size();
         a.ntasks = (int)g.tasks.size();
         a.nred = g.nred < a.ntasks ? g.nred : a.ntasks;
+        a.rows = a.nred > 0 ? 1 : 0;
         // a batch of one section derives its tasks from `parts` (task_of) with
         // the same split as the task list built by the planner
         a.parts = g.parts;

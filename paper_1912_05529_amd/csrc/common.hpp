@@ -56,6 +56,7 @@ struct BatchArgs {
     const float2* tab;     // [nk][M+1] complex64 half-taps
     float* trash;          // [ldp_max] sink for partial rows of idle sub-groups
     int nsec, nitems, ntasks, nred;
+    int rows;              // frequency workgroups write and publish partial rows
     int parts;             // x-parts per block (nsec == 1)
     int nk, M;
     double dk;             // table spacing (kmax-kmin)/(nk-1)
@@ -183,6 +184,10 @@ int launch_demigrate_reg(const AdjArgs& a, hipStream_t s);
 int launch_transform(const float* section, int nx, int nt, double dt, const double* omega,
                      int nw, float2* out, float* B, hipStream_t s);
 int launch_image(const float2* wf, double* row, int nx, int nw, hipStream_t s);
+// Image rows of depth steps [s0, s1) of one section from its partial rows
+// ([step][nw][ldp] floats), after the depth-stepping launch.
+int launch_rows(const float* part, double* rows, int s0, int s1, int nx, int nw, int ldp,
+                hipStream_t s);
 
 // One 3-D depth step (device pointers; planes are [nw][nx][ny]).
 struct Step3dArgs {

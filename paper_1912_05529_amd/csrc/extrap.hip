@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
 __global__ void __launch_bounds__(256) k_extrap_general(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
-    const bool rows_on = a.nred > 0;
+    const bool rows_on = a.rows != 0;
     if (rows_on && (int)blockIdx.x >= a.nitems) {
         reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
         return;
@@ -554,10 +554,36 @@ __global__ void k_zero(int* p, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// Image rows of depth steps [s0, s1) from their partial rows, once the
+// depth-stepping launch is over: one thread per point, the frequencies added in
+// increasing order in FP64, the order of the reducer workgroups, so a row is the
+// same whichever of the two forms it.  Small workgroups spread the rows over
+// every CU; 16 loads in flight per thread.
+__global__ void __launch_bounds__(64) k_rows(const float* __restrict__ part,
+                                             double* __restrict__ rows, int s0, int nx, int nw,
+                                             int ldp)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const int st = s0 + blockIdx.y;
+    const float* p = part + (size_t)st * nw * ldp + x;
+    double acc = 0.0;
+    int r = 0;
+    for (; r + 16 <= nw; r += 16) {
+        float v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = p[(size_t)(r + j) * ldp];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += (double)v[j];
+    }
+    for (; r < nw; ++r) acc += (double)p[(size_t)r * ldp];
+    rows[(size_t)st * nx + x] = acc;
+}
+
 template <int M>
 int launch_fast(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
 {
-    if (a.nred > 0)
+    if (a.rows)
         hipLaunchKernelGGL((k_extrap_fast<M, true>), dim3(a.nitems + a.nred), dim3(threads), lds,
                            s, a);
     else
@@ -568,7 +594,7 @@ int launch_fast(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
 template <int M>
 int launch_wide(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
 {
-    if (a.nred > 0)
+    if (a.rows)
         hipLaunchKernelGGL((k_extrap_wide<M, true>), dim3(a.nitems + a.nred), dim3(threads), lds,
                            s, a);
     else
@@ -649,6 +675,15 @@ int launch_zero(int* p, int n, hipStream_t s)
     if (blocks > 64) blocks = 64;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+int launch_rows(const float* part, double* rows, int s0, int s1, int nx, int nw, int ldp,
+                hipStream_t s)
+{
+    if (s1 <= s0) return MIG_OK;
+    dim3 grid((nx + 63) / 64, s1 - s0);
+    hipLaunchKernelGGL(k_rows, grid, dim3(64), 0, s, part, rows, s0, nx, nw, ldp);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
