@@ -95,6 +95,13 @@ int parts_for(int total_blocks, int nred, int max_nx)
     return p < 1 ? 1 : p;
 }
 
+// x-parts per published block of a single section: parts 32 points wide, so
+// that a task is one pair of points per thread of a 512-thread workgroup for
+// the 32 steps of a block.  A task then takes about half a block period, and
+// the reducers keep up with the frequency workgroups instead of trailing them
+// by a task's length at the end of the launch.
+int parts_single(int nx) { return (nx + 31) / 32; }
+
 // Frequencies per workgroup for one section in the register-tap kernel with two
 // outputs per thread: `want` if given (clamped to what fits), else 1.
 int omegas_per_group(int kind, int nx, int want)
@@ -176,7 +183,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
         a.rows = rows ? 1 : 0;
         if (rows && nb > 1) {
             const int nred = reducer_count(nitems, tn.nred);
-            a.parts = parts_for(nb - 1, nred, nx);
+            a.parts = parts_single(nx);
             a.ntasks = (nb - 1) * a.parts;
             a.nred = nred < a.ntasks ? nred : a.ntasks;
         } else {
