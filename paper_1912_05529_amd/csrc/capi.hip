@@ -85,22 +85,12 @@ int reducer_count(int nprod, int want)
 
 int blocks_of(int nsteps) { return (nsteps + kPublish - 1) / kPublish; }
 
-// x-parts per published block: enough tasks for about two per reducer when
-// there are few blocks, parts at least 128 points wide.
-int parts_for(int total_blocks, int nred, int max_nx)
-{
-    int p = (2 * nred + total_blocks - 1) / total_blocks;
-    int cap = max_nx / 128 > 1 ? max_nx / 128 : 1;
-    if (p > cap) p = cap;
-    return p < 1 ? 1 : p;
-}
-
-// x-parts per published block of a single section: parts 32 points wide, so
+// x-parts per published block of a section: parts 32 points wide, so
 // that a task is one pair of points per thread of a 512-thread workgroup for
 // the 32 steps of a block.  A task then takes about half a block period, and
 // the reducers keep up with the frequency workgroups instead of trailing them
 // by a task's length at the end of the launch.
-int parts_single(int nx) { return (nx + 31) / 32; }
+int parts_of(int nx) { return (nx + 31) / 32; }
 
 // Frequencies per workgroup for one section in the register-tap kernel with two
 // outputs per thread: `want` if given (clamped to what fits), else 1.
@@ -183,7 +173,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
         a.rows = rows ? 1 : 0;
         if (rows && nb > 1) {
             const int nred = reducer_count(nitems, tn.nred);
-            a.parts = parts_single(nx);
+            a.parts = parts_of(nx);
             a.ntasks = (nb - 1) * a.parts;
             a.nred = nred < a.ntasks ? nred : a.ntasks;
         } else {
@@ -300,18 +290,20 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
         for (int si : order)
             for (int r0 = 0; r0 < g.secs[si].nw; r0 += g.secs[si].G) g.items.push_back(ItemDev{si, r0});
         // Reducer tasks block-major across sections (production order).
-        int total_blocks = 0;
-        for (const SecDev& S : g.secs) total_blocks += blocks_of(S.nsteps);
         g.nred = reducer_count((int)g.items.size(), tn.nred);
-        const int parts = parts_for(total_blocks, g.nred, g.max_nx);
-        g.parts = parts;
+        g.parts = parts_of(g.secs[0].nx);  // read by a batch of one section only
         for (int c = 0; c < blocks_of(g.max_rows); ++c)
             for (int si : order) {
                 if (c >= blocks_of(g.secs[si].nsteps)) continue;
                 const int nx = g.secs[si].nx;
+                const int parts = parts_of(nx);
                 const int span = ((nx + parts - 1) / parts + 1) & ~1;
-                for (int x0 = 0; x0 < nx; x0 += span)
+                // exactly `parts` tasks per block (trailing ones may be empty), as
+                // task_of derives them for a batch of one section
+                for (int p = 0; p < parts; ++p) {
+                    const int x0 = p * span < nx ? p * span : nx;
                     g.tasks.push_back(TaskDev{si, c, x0, x0 + span < nx ? x0 + span : nx});
+                }
             }
         g.desc_bytes = g.secs.size() * sizeof(SecDev) + g.items.size() * sizeof(ItemDev) +
                        g.tasks.size() * sizeof(TaskDev);
