@@ -76,12 +76,20 @@ __global__ void __launch_bounds__(512) k_demigrate(AdjArgs a)
 
 // Register-tap form (nx <= 2 * kAdjThreads, M <= kAdjMaxM): each thread owns
 // two adjacent points y, y+1 of the frequency, keeps their Q values and their
-// (M+1) taps in registers (refilled only where the slowness changes going up
-// a step), writes the products conj(h_y[m]) q[y] of every tap m to LDS in one
-// pass, and after one barrier gathers its two outputs from them.  The plane Q
-// never leaves registers; two barriers per depth step.
+// (M+1) taps in registers, writes the products conj(h_y[m]) q[y] of every tap
+// m to LDS in one pass, and after one barrier gathers its two outputs from
+// them.  The plane Q never leaves registers; two barriers per depth step.
+// Taps come in two sets that alternate between steps: while a step runs on
+// one set, the other is refilled for the next step (only where the slowness
+// differs from the row two steps away, flag in the slowness sign bit), so the
+// L2 latency of a refill hides behind a whole step.
 constexpr int kAdjThreads = 512;
 constexpr int kAdjMaxM = 17;
+
+__device__ __forceinline__ void wait_vmem()
+{
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt(0) only
+}
 
 template <int M>
 __device__ __forceinline__ void load_taps_adj(float2 (&h)[M + 1], const float2* __restrict__ row)
@@ -90,105 +98,129 @@ __device__ __forceinline__ void load_taps_adj(float2 (&h)[M + 1], const float2* 
     for (int m = 0; m <= M; ++m) h[m] = row[m];
 }
 
+// Per-thread state of the register-tap kernel.
+struct AdjLane {
+    int y0, c0, c1;
+    bool live0, live1;
+    double ar;
+    double fl0, fl1;  // slowness of row k+1 (its flag: differs from row k-1)
+    double sv0, sv1;  // slowness of row k-1 (taps of step k-1)
+    double i0, i1;    // image row k
+};
+
+template <int M>
+__device__ __forceinline__ void adj_step(const AdjArgs& a, float2* G, int LG, AdjLane& L, int k,
+                                         float2 (&hc0)[M + 1], float2 (&hc1)[M + 1],
+                                         float2 (&ho0)[M + 1], float2 (&ho1)[M + 1], float2& q0,
+                                         float2& q1, bool first)
+{
+    // everything issued during the previous step has arrived: the taps of
+    // this step and the values prefetched for it
+    wait_vmem();
+    if (!first && k >= 1) {
+        if (slowness_changed(L.fl0))
+            load_taps_adj<M>(ho0, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk,
+                                                                    slowness_value(L.sv0)) * (M + 1));
+        if (slowness_changed(L.fl1))
+            load_taps_adj<M>(ho1, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk,
+                                                                    slowness_value(L.sv1)) * (M + 1));
+    }
+    const double ci0 = L.i0, ci1 = L.i1;
+    // prefetch for step k-1, branch-free (rows clamped; values past the top
+    // are never used), so that nothing consumes them before the next step
+    const int ks = k >= 2 ? k - 2 : 0, ki = k >= 1 ? k - 1 : 0;
+    L.fl0 = a.slow[(size_t)k * a.ldp + L.c0];
+    L.fl1 = a.slow[(size_t)k * a.ldp + L.c1];
+    L.sv0 = a.slow[(size_t)ks * a.ldp + L.c0];
+    L.sv1 = a.slow[(size_t)ks * a.ldp + L.c1];
+    L.i0 = a.image[(size_t)ki * a.nx + L.c0];
+    L.i1 = a.image[(size_t)ki * a.nx + L.c1];
+    if (L.live0) {
+        // q1 = 0 when y0 + 1 is past the end: the store keeps that border zero
+        float2* g = G + M + L.y0;
+#pragma unroll
+        for (int m = 0; m <= M; ++m) {
+            g[(size_t)m * LG] = cmul_conj(hc0[m], q0);
+            g[(size_t)m * LG + 1] = cmul_conj(hc1[m], q1);
+        }
+    }
+    __syncthreads();
+    // Two partial sums per output (taps m odd / m even) halve the chain of
+    // dependent additions.
+    float2 a0 = make_float2((float)ci0, 0.0f), a1 = make_float2((float)ci1, 0.0f);
+    if (L.live0) {
+        const float2* g = G + M + L.y0;
+        float2 e = g[0], o = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int m = 1; m <= M; ++m) {
+            const float2* gm = g + (size_t)m * LG;
+            float2& t = (m & 1) ? o : e;
+            t.x += gm[-m].x + gm[m].x;
+            t.y += gm[-m].y + gm[m].y;
+        }
+        a0.x += e.x + o.x;
+        a0.y += e.y + o.y;
+    }
+    if (L.live1) {
+        const float2* g = G + M + L.y0 + 1;
+        float2 e = g[0], o = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int m = 1; m <= M; ++m) {
+            const float2* gm = g + (size_t)m * LG;
+            float2& t = (m & 1) ? o : e;
+            t.x += gm[-m].x + gm[m].x;
+            t.y += gm[-m].y + gm[m].y;
+        }
+        a1.x += e.x + o.x;
+        a1.y += e.y + o.y;
+    }
+    __syncthreads();
+    q0 = L.live0 ? a0 : make_float2(0.0f, 0.0f);
+    q1 = L.live1 ? a1 : make_float2(0.0f, 0.0f);
+}
+
 template <int M>
 __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
 {
     extern __shared__ float4 smem4[];
     float2* G = reinterpret_cast<float2*>(smem4);  // [M+1][nx + 2M], zero outside [M, M + nx)
     const int nx = a.nx, LG = nx + 2 * M, r = blockIdx.x;
-    const double ar = a.omega[r] / a.dk;
-    const int y0 = 2 * threadIdx.x;
-    const bool live0 = y0 < nx, live1 = y0 + 1 < nx;
+    AdjLane L;
+    L.ar = a.omega[r] / a.dk;
+    L.y0 = 2 * threadIdx.x;
+    L.live0 = L.y0 < nx;
+    L.live1 = L.y0 + 1 < nx;
+    L.c0 = L.live0 ? L.y0 : 0;
+    L.c1 = L.live1 ? L.y0 + 1 : 0;
 
     for (int i = threadIdx.x; i < (M + 1) * LG; i += blockDim.x) G[i] = make_float2(0.0f, 0.0f);
-    float2 q0 = make_float2(live0 ? (float)a.image[(size_t)(a.nz - 1) * nx + y0] : 0.0f, 0.0f);
-    float2 q1 = make_float2(live1 ? (float)a.image[(size_t)(a.nz - 1) * nx + y0 + 1] : 0.0f, 0.0f);
-    float2 h0[M + 1], h1[M + 1];
-    if (a.nz > 1) {
-        const double* srow = a.slow + (size_t)(a.nz - 2) * a.ldp;
-        load_taps_adj<M>(h0, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
-                                                               slowness_value(srow[live0 ? y0 : 0])) * (M + 1));
-        load_taps_adj<M>(h1, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
-                                                               slowness_value(srow[live1 ? y0 + 1 : 0])) * (M + 1));
+    float2 q0 = make_float2(L.live0 ? (float)a.image[(size_t)(a.nz - 1) * nx + L.y0] : 0.0f, 0.0f);
+    float2 q1 = make_float2(L.live1 ? (float)a.image[(size_t)(a.nz - 1) * nx + L.y0 + 1] : 0.0f, 0.0f);
+    // set A: taps of the first step (row nz-2); set B: of the second (row nz-3)
+    float2 hA0[M + 1], hA1[M + 1], hB0[M + 1], hB1[M + 1];
+    int k = a.nz - 2;
+    if (k >= 0) {
+        const double* s0 = a.slow + (size_t)k * a.ldp;
+        load_taps_adj<M>(hA0, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s0[L.c0])) * (M + 1));
+        load_taps_adj<M>(hA1, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s0[L.c1])) * (M + 1));
+        const double* s1 = a.slow + (size_t)(k >= 1 ? k - 1 : k) * a.ldp;
+        load_taps_adj<M>(hB0, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s1[L.c0])) * (M + 1));
+        load_taps_adj<M>(hB1, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk, slowness_value(s1[L.c1])) * (M + 1));
+        L.i0 = L.live0 ? a.image[(size_t)k * nx + L.c0] : 0.0;
+        L.i1 = L.live1 ? a.image[(size_t)k * nx + L.c1] : 0.0;
     }
+    L.fl0 = L.fl1 = L.sv0 = L.sv1 = 0.0;
     __syncthreads();
 
-    // Values for the coming step k, loaded one step ahead: the flag of row k
-    // (differs from row k-1), the slowness of row k-1 (taps of the next
-    // step) and the image row k.
-    const int c0 = live0 ? y0 : 0, c1 = live1 ? y0 + 1 : 0;
-    auto slow_at = [&](int row, int c) { return row >= 0 ? a.slow[(size_t)row * a.ldp + c] : 0.0; };
-    auto img_at = [&](int row, int c, bool live) {
-        return live && row >= 0 ? a.image[(size_t)row * nx + c] : 0.0;
-    };
-    int k = a.nz - 2;
-    double fk0 = slow_at(k, c0), fk1 = slow_at(k, c1);
-    double su0 = slow_at(k - 1, c0), su1 = slow_at(k - 1, c1);
-    double i0 = img_at(k, c0, live0), i1 = img_at(k, c1, live1);
-    for (; k >= 0; --k) {
-        if (live0) {
-            // q1 = 0 when y0 + 1 is past the end: the store keeps that border zero
-            float2* g = G + M + y0;
-#pragma unroll
-            for (int m = 0; m <= M; ++m) {
-                g[(size_t)m * LG] = cmul_conj(h0[m], q0);
-                g[(size_t)m * LG + 1] = cmul_conj(h1[m], q1);
-            }
-        }
-        // The taps are free now: refill them for step k-1 where the row
-        // changes, and prefetch the next step's slowness and image values, so
-        // the loads overlap the barrier and the gather.
-        if (k >= 1) {
-            if (slowness_changed(fk0))
-                load_taps_adj<M>(h0, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
-                                                                       slowness_value(su0)) * (M + 1));
-            if (slowness_changed(fk1))
-                load_taps_adj<M>(h1, a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
-                                                                       slowness_value(su1)) * (M + 1));
-        }
-        const double ci0 = i0, ci1 = i1;
-        fk0 = slow_at(k - 1, c0);
-        fk1 = slow_at(k - 1, c1);
-        su0 = slow_at(k - 2, c0);
-        su1 = slow_at(k - 2, c1);
-        i0 = img_at(k - 1, c0, live0);
-        i1 = img_at(k - 1, c1, live1);
-        __syncthreads();
-        // Two partial sums per output (taps m odd / m even) halve the chain of
-        // dependent additions.
-        float2 a0 = make_float2((float)ci0, 0.0f), a1 = make_float2((float)ci1, 0.0f);
-        if (live0) {
-            const float2* g = G + M + y0;
-            float2 e = g[0], o = make_float2(0.0f, 0.0f);
-#pragma unroll
-            for (int m = 1; m <= M; ++m) {
-                const float2* gm = g + (size_t)m * LG;
-                float2& t = (m & 1) ? o : e;
-                t.x += gm[-m].x + gm[m].x;
-                t.y += gm[-m].y + gm[m].y;
-            }
-            a0.x += e.x + o.x;
-            a0.y += e.y + o.y;
-        }
-        if (live1) {
-            const float2* g = G + M + y0 + 1;
-            float2 e = g[0], o = make_float2(0.0f, 0.0f);
-#pragma unroll
-            for (int m = 1; m <= M; ++m) {
-                const float2* gm = g + (size_t)m * LG;
-                float2& t = (m & 1) ? o : e;
-                t.x += gm[-m].x + gm[m].x;
-                t.y += gm[-m].y + gm[m].y;
-            }
-            a1.x += e.x + o.x;
-            a1.y += e.y + o.y;
-        }
-        __syncthreads();
-        q0 = live0 ? a0 : make_float2(0.0f, 0.0f);
-        q1 = live1 ? a1 : make_float2(0.0f, 0.0f);
+    bool first = true;
+    for (; k >= 0; k -= 2) {
+        adj_step<M>(a, G, LG, L, k, hA0, hA1, hB0, hB1, q0, q1, first);
+        first = false;
+        if (k == 0) break;
+        adj_step<M>(a, G, LG, L, k - 1, hB0, hB1, hA0, hA1, q0, q1, false);
     }
-    if (live0) a.out[(size_t)y0 * a.nw + r] = q0;
-    if (live1) a.out[(size_t)(y0 + 1) * a.nw + r] = q1;
+    if (L.live0) a.out[(size_t)L.y0 * a.nw + r] = q0;
+    if (L.live1) a.out[(size_t)(L.y0 + 1) * a.nw + r] = q1;
 }
 
 template <int M>

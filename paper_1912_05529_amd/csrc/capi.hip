@@ -587,10 +587,10 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
         sa.one.nx = nx;
         sa.one.nsteps = nz - 1;
         sa.one.ldp = a.ldp;
-        // change flags against the previous row: walking depth upward, the
-        // register-tap kernel refills a point's taps where its row differs
-        // from the row above
-        int rc = launch_slowness(sa, nz - 1, a.ldp, 1, s);
+        // change flags two rows apart: walking depth upward with two tap sets
+        // that alternate between steps, the register-tap kernel refills a
+        // point's taps where its row differs from the row two steps below
+        int rc = launch_slowness(sa, nz - 1, a.ldp, 2, s);
         if (rc != MIG_OK) return rc;
     }
     return reg ? launch_demigrate_reg(a, s) : launch_demigrate(a, s);
