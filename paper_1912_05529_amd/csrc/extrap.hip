@@ -27,14 +27,16 @@
 //     small pre-pass (shared by all frequencies) instead of once per refill.
 //   * The image row needs a sum over frequencies, i.e. across workgroups.
 //     Each frequency sub-group writes Re of its new plane (float32, exact) to a
-//     partial buffer [step][omega][x]; every kPublish steps the workgroup
-//     publishes its progress (agent-scope release + counter increment).
-//     Reducer workgroups in the same launch -- on CUs the frequency workgroups
-//     leave idle -- wait for a block of steps to be published by every
-//     workgroup of the section and sum it over omega in increasing order in
-//     FP64, so images are run-to-run identical and the reduction overlaps the
-//     extrapolation.  Frequency workgroups never wait on anyone; reducer waits
-//     are bounded (a stall of kStallTicks writes NaN rows instead of hanging).
+//     partial buffer [step][omega][x], write-through; every kPublish steps the
+//     workgroup publishes its progress (its stores complete, then a counter
+//     increment).  Reducer workgroups in the same launch -- on CUs the
+//     frequency workgroups leave idle -- wait for a block of steps to be
+//     published by every workgroup of the section, acquire, and sum it over
+//     omega in increasing order in FP64, so images are run-to-run identical
+//     and the reduction overlaps the extrapolation; the last block is summed
+//     after the launch (k_rows) by the whole GPU.  Frequency workgroups never
+//     wait on anyone; reducer waits are bounded (a stall of kStallTicks writes
+//     NaN rows instead of hanging).
 #include "common.hpp"
 
 namespace mig {
@@ -67,8 +69,8 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b)
 }
 
 // Partial image rows are stored write-through (agent-scope relaxed atomic
-// stores): reducers on other XCDs read them after the block's release, and
-// the release then finds nothing of them left to write back from L2.
+// stores): reducers on other XCDs read them once their block is counted, and
+// nothing of them is left in this XCD's L2 to write back first.
 __device__ __forceinline__ void store_partial2(float* p, float a, float b)
 {
     const unsigned long long u =
@@ -179,14 +181,15 @@ __global__ void k_slowness(BatchArgs a, int dist)
 }
 
 // Thread 0 of a frequency workgroup, after a barrier that follows the stores of
-// the partial rows of block c: release them at agent scope and count.  Every
-// wave waits for its own stores to complete before that barrier
-// (wait_vmem_all): the release's wait covers only the stores of thread 0's
-// wave.
+// the partial rows of block c: count the block.  The partial rows are stored
+// write-through (agent-scope atomic stores) and every wave waits for its own
+// stores to complete before that barrier (wait_vmem_all), so when the counter
+// moves the rows are already where other XCDs read them.  No release fence:
+// at agent scope it would write back the whole L2 of the XCD, which the
+// barrier after the next step would make every wave of the workgroup wait for.
 __device__ __forceinline__ void publish_block(const SecDev& S, int c)
 {
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(as_global(S.cnt + c), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -505,7 +508,9 @@ __global__ void __launch_bounds__(256) k_extrap_general(BatchArgs a)
             float2 acc = cmulf(h[0], src[x]);
             for (int n = 1; n <= M; ++n) acc = cfmaf(h[n], cadd(src[x - n], src[x + n]), acc);
             dst[x] = acc;
-            if (rows_on && live) *as_global(S.part + ((size_t)k * S.nw + r) * S.ldp + x) = acc.x;
+            if (rows_on && live)  // write-through, as store_partial2
+                __hip_atomic_store(as_global(S.part + ((size_t)k * S.nw + r) * S.ldp + x), acc.x,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const bool publish = rows_on && ((k + 1) % kPublish == 0 || k + 1 == S.nsteps);
         if (publish) wait_vmem_all();
