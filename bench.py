@@ -186,7 +186,7 @@ def headline(torch, mig, synth, dev, args):
     flop_alg = outputs * (8 * (M + 1) + 2 * M)
     value = tap_macs / (ms_step * 1e-3) / 1e9
     achieved = flop_alg / (ms_kernel * 1e-3) / 1e12
-    traffic = profiled_traffic(args, "k_extrap_fast<17,true> config2")
+    traffic = profiled_traffic(args, "mig_extrapolate config2")
     res = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -217,8 +217,9 @@ def headline(torch, mig, synth, dev, args):
         "roofline": {
             "bound": "alu",
             "kernel": "depth-stepping launch: register-tap kernel, all %d depth steps, fused "
-                      "image rows (mig_extrapolate with rows; includes its two small "
-                      "pre-kernels)" % (nz - 1),
+                      "image rows (mig_extrapolate with rows: its two small pre-kernels, "
+                      "the depth-stepping kernel with reducer workgroups, and the row "
+                      "kernel of the last published block)" % (nz - 1),
             "achieved": round(achieved, 3),
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",

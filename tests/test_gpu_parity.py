@@ -190,14 +190,18 @@ def test_extrapolate_zero_steps_and_errors(tables):
     assert e.value.code == mig.MIG_E_WORKSPACE
 
 
-@pytest.mark.parametrize("nx,nw,nsteps", [(1024, 600, 20), (130, 37, 33), (2000, 9, 17)])
-def test_fused_reduction_rows_match_oracle(nx, nw, nsteps, tables):
+@pytest.mark.parametrize("nx,nw,nsteps,ntaps", [(1024, 600, 20, 35), (130, 37, 33, 35),
+                                               (2000, 9, 17, 35), (1024, 300, 97, 35),
+                                               (2100, 40, 40, 35), (300, 60, 70, 41)])
+def test_fused_reduction_rows_match_oracle(nx, nw, nsteps, ntaps, tables):
     """Image rows formed inside the depth-stepping launch (reducer workgroups)
-    for more frequency workgroups than CUs, for several publish blocks with a
-    ragged last block, and for the four-outputs-per-thread kernel."""
-    sec = synth.random_case(3000 + nx + nw, nx, nsteps + 1, nw, ntaps=35, nk=256)
+    and, for the last published block, after it: more frequency workgroups than
+    CUs, several publish blocks with a ragged last block, the
+    four-outputs-per-thread kernel and the general kernel (nx > 2048, N > 35)."""
+    sec = synth.random_case(3000 + nx + nw, nx, nsteps + 1, nw, ntaps=ntaps, nk=256)
     (ot, _, _, _), g = tables(sec.desc)
-    print("fused rows nx=%d nw=%d nsteps=%d kind=%d" % (nx, nw, nsteps, mig.kernel_kind(nx, 35)),
+    print("fused rows nx=%d nw=%d nsteps=%d N=%d kind=%d" % (nx, nw, nsteps, ntaps,
+                                                           mig.kernel_kind(nx, ntaps)),
           flush=True)
     t = upload(sec)
     vel = t["vel"][:nsteps].contiguous()
