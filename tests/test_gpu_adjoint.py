@@ -38,6 +38,29 @@ def test_demigrate_matches_oracle_adjoint(small):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("nx,nz,nw,ntaps,layered", [
+    (64, 2, 4, 35, True), (64, 3, 4, 35, True), (130, 4, 5, 35, True), (257, 5, 3, 35, False),
+    (1024, 40, 6, 35, True), (1023, 37, 5, 11, True), (300, 20, 4, 41, True)])
+def test_demigrate_shapes_match_oracle(nx, nz, nw, ntaps, layered):
+    """Demigration against the FP64 oracle for one to a few dozen depth steps
+    (both tap sets of the register-tap kernel, odd and even step counts), a
+    layered model (taps kept across steps where the slowness repeats), an odd
+    nx, and the general kernel (N = 41)."""
+    sec = synth.random_case(1700 + nx + nz, nx, nz, nw, ntaps=ntaps, nk=256, layered=layered)
+    print("demigrate nx=%d nz=%d nw=%d N=%d layered=%s" % (nx, nz, nw, ntaps, layered), flush=True)
+    tab = mig.design_table(sec.desc, dev())
+    t = upload(sec)
+    rng = np.random.default_rng(nx + nz)
+    img = rng.standard_normal((nz, nx))
+    got = mig.demigrate(torch.from_numpy(img).to(dev()), t["vel"], t["omega"], tab["tab32"],
+                        sec.desc).cpu().numpy()
+    ot = oracle.design_table(sec.desc)[0]
+    ref = oracle.demigrate(sec.desc, ot, sec.omega, sec.vel, img)
+    err = rel_l2(got, ref)
+    print("  rel L2 %.3e" % err)
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("nx,nz,nw,ntaps", [(64, 64, 16, 35), (1024, 40, 12, 35),
                                             (300, 33, 7, 25), (2100, 5, 3, 35), (1, 4, 2, 35)])
 def test_dot_product(nx, nz, nw, ntaps):
