@@ -82,9 +82,24 @@ __global__ void __launch_bounds__(512) k_demigrate(AdjArgs a)
 // Taps come in two sets that alternate between steps: while a step runs on
 // one set, the other is refilled for the next step (only where the slowness
 // differs from the row two steps away, flag in the slowness sign bit), so the
-// L2 latency of a refill hides behind a whole step.
+// L2 latency of a refill hides behind a whole step.  The products live in
+// two LDS arrays, one for even and one for odd points, so that every LDS
+// access of a wave -- the stores of a thread's two points and each gather of
+// a neighbour at any shift -- touches consecutive 8-byte words across the
+// lanes: free of bank conflicts, which with the points interleaved took half
+// of the LDS cycles.
 constexpr int kAdjThreads = 512;
 constexpr int kAdjMaxM = 17;
+
+// Halo, in point pairs, on each side of the product arrays: the gather reaches
+// (M+1)/2 pairs away.
+__host__ __device__ constexpr int adj_halo(int M) { return (M + 2) / 2; }
+
+// LDS bytes of the register-tap kernel: products at even and odd points.
+__host__ __device__ constexpr size_t adj_reg_lds(int nx, int M)
+{
+    return (size_t)2 * (M + 1) * ((nx + 1) / 2 + 2 * adj_halo(M)) * sizeof(float2);
+}
 
 __device__ __forceinline__ void wait_vmem()
 {
@@ -109,11 +124,12 @@ struct AdjLane {
 };
 
 template <int M>
-__device__ __forceinline__ void adj_step(const AdjArgs& a, float2* G, int LG, AdjLane& L, int k,
+__device__ __forceinline__ void adj_step(const AdjArgs& a, float2* G, int LP, AdjLane& L, int k,
                                          float2 (&hc0)[M + 1], float2 (&hc1)[M + 1],
                                          float2 (&ho0)[M + 1], float2 (&ho1)[M + 1], float2& q0,
                                          float2& q1, bool first)
 {
+    constexpr int kH = adj_halo(M);
     // everything issued during the previous step has arrived: the taps of
     // this step and the values prefetched for it
     wait_vmem();
@@ -135,44 +151,58 @@ __device__ __forceinline__ void adj_step(const AdjArgs& a, float2* G, int LG, Ad
     L.sv1 = a.slow[(size_t)ks * a.ldp + L.c1];
     L.i0 = a.image[(size_t)ki * a.nx + L.c0];
     L.i1 = a.image[(size_t)ki * a.nx + L.c1];
+    // E[m][H + p] = g_m[2p], O[m][H + p] = g_m[2p + 1]: thread t owns pair t.
+    // q1 = 0 when y0 + 1 is past the end: the store keeps that point zero
+    float2* E = G;
+    float2* O = G + (size_t)(M + 1) * LP;
+    const int t = threadIdx.x;
     if (L.live0) {
-        // q1 = 0 when y0 + 1 is past the end: the store keeps that border zero
-        float2* g = G + M + L.y0;
 #pragma unroll
         for (int m = 0; m <= M; ++m) {
-            g[(size_t)m * LG] = cmul_conj(hc0[m], q0);
-            g[(size_t)m * LG + 1] = cmul_conj(hc1[m], q1);
+            E[(size_t)m * LP + kH + t] = cmul_conj(hc0[m], q0);
+            O[(size_t)m * LP + kH + t] = cmul_conj(hc1[m], q1);
         }
     }
     __syncthreads();
-    // Two partial sums per output (taps m odd / m even) halve the chain of
+    // out[2t] and out[2t+1] = g_0 + sum_m g_m[x - m] + g_m[x + m]: for m = 2s the
+    // neighbours of 2t are even points (pairs t -+ s) and those of 2t+1 odd
+    // ones; for m = 2s+1 they swap (pairs t-s-1, t+s and t-s, t+s+1).  Two
+    // partial sums per output (taps m odd / m even) halve the chain of
     // dependent additions.
     float2 a0 = make_float2((float)ci0, 0.0f), a1 = make_float2((float)ci1, 0.0f);
     if (L.live0) {
-        const float2* g = G + M + L.y0;
-        float2 e = g[0], o = make_float2(0.0f, 0.0f);
+        const float2* e = E + kH + t;
+        const float2* o = O + kH + t;
+        float2 se0 = e[0], so0 = make_float2(0.0f, 0.0f);
+        float2 se1 = o[0], so1 = make_float2(0.0f, 0.0f);
 #pragma unroll
         for (int m = 1; m <= M; ++m) {
-            const float2* gm = g + (size_t)m * LG;
-            float2& t = (m & 1) ? o : e;
-            t.x += gm[-m].x + gm[m].x;
-            t.y += gm[-m].y + gm[m].y;
+            const int sh = m >> 1;
+            const float2* em = e + (size_t)m * LP;
+            const float2* om = o + (size_t)m * LP;
+            float2 l0, r0, l1, r1;
+            if (m & 1) {
+                l0 = om[-sh - 1];
+                r0 = om[sh];
+                l1 = em[-sh];
+                r1 = em[sh + 1];
+            } else {
+                l0 = em[-sh];
+                r0 = em[sh];
+                l1 = om[-sh];
+                r1 = om[sh];
+            }
+            float2& u0 = (m & 1) ? so0 : se0;
+            float2& u1 = (m & 1) ? so1 : se1;
+            u0.x += l0.x + r0.x;
+            u0.y += l0.y + r0.y;
+            u1.x += l1.x + r1.x;
+            u1.y += l1.y + r1.y;
         }
-        a0.x += e.x + o.x;
-        a0.y += e.y + o.y;
-    }
-    if (L.live1) {
-        const float2* g = G + M + L.y0 + 1;
-        float2 e = g[0], o = make_float2(0.0f, 0.0f);
-#pragma unroll
-        for (int m = 1; m <= M; ++m) {
-            const float2* gm = g + (size_t)m * LG;
-            float2& t = (m & 1) ? o : e;
-            t.x += gm[-m].x + gm[m].x;
-            t.y += gm[-m].y + gm[m].y;
-        }
-        a1.x += e.x + o.x;
-        a1.y += e.y + o.y;
+        a0.x += se0.x + so0.x;
+        a0.y += se0.y + so0.y;
+        a1.x += se1.x + so1.x;
+        a1.y += se1.y + so1.y;
     }
     __syncthreads();
     q0 = L.live0 ? a0 : make_float2(0.0f, 0.0f);
@@ -183,8 +213,11 @@ template <int M>
 __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
 {
     extern __shared__ float4 smem4[];
-    float2* G = reinterpret_cast<float2*>(smem4);  // [M+1][nx + 2M], zero outside [M, M + nx)
-    const int nx = a.nx, LG = nx + 2 * M, r = blockIdx.x;
+    // [2][M+1][LP]: products at even and odd points, LP = pairs + 2 kH, zero
+    // outside the points of the section
+    constexpr int kH = adj_halo(M);
+    float2* G = reinterpret_cast<float2*>(smem4);
+    const int nx = a.nx, LP = (nx + 1) / 2 + 2 * kH, r = blockIdx.x;
     AdjLane L;
     L.ar = a.omega[r] / a.dk;
     L.y0 = 2 * threadIdx.x;
@@ -193,7 +226,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
     L.c0 = L.live0 ? L.y0 : 0;
     L.c1 = L.live1 ? L.y0 + 1 : 0;
 
-    for (int i = threadIdx.x; i < (M + 1) * LG; i += blockDim.x) G[i] = make_float2(0.0f, 0.0f);
+    for (int i = threadIdx.x; i < 2 * (M + 1) * LP; i += blockDim.x) G[i] = make_float2(0.0f, 0.0f);
     float2 q0 = make_float2(L.live0 ? (float)a.image[(size_t)(a.nz - 1) * nx + L.y0] : 0.0f, 0.0f);
     float2 q1 = make_float2(L.live1 ? (float)a.image[(size_t)(a.nz - 1) * nx + L.y0 + 1] : 0.0f, 0.0f);
     // set A: taps of the first step (row nz-2); set B: of the second (row nz-3)
@@ -214,10 +247,10 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
 
     bool first = true;
     for (; k >= 0; k -= 2) {
-        adj_step<M>(a, G, LG, L, k, hA0, hA1, hB0, hB1, q0, q1, first);
+        adj_step<M>(a, G, LP, L, k, hA0, hA1, hB0, hB1, q0, q1, first);
         first = false;
         if (k == 0) break;
-        adj_step<M>(a, G, LG, L, k - 1, hB0, hB1, hA0, hA1, q0, q1, false);
+        adj_step<M>(a, G, LP, L, k - 1, hB0, hB1, hA0, hA1, q0, q1, false);
     }
     if (L.live0) a.out[(size_t)L.y0 * a.nw + r] = q0;
     if (L.live1) a.out[(size_t)(L.y0 + 1) * a.nw + r] = q1;
@@ -241,13 +274,12 @@ bool adjoint_uses_registers(int nx, int M, size_t lds_limit)
 {
     // M >= 1: the pair store of the last point of an odd nx lands on the
     // right border, which then exists
-    return nx <= 2 * kAdjThreads && M >= 1 && M <= kAdjMaxM &&
-           (size_t)(M + 1) * (nx + 2 * M) * sizeof(float2) <= lds_limit;
+    return nx <= 2 * kAdjThreads && M >= 1 && M <= kAdjMaxM && adj_reg_lds(nx, M) <= lds_limit;
 }
 
 int launch_demigrate_reg(const AdjArgs& a, hipStream_t s)
 {
-    const size_t lds = (size_t)(a.M + 1) * (a.nx + 2 * a.M) * sizeof(float2);
+    const size_t lds = adj_reg_lds(a.nx, a.M);
     switch (a.M) {
 #define MIG_ADJ_CASE(m) \
     case m: return launch_reg<m>(a, lds, s);
