@@ -67,6 +67,27 @@ __device__ __forceinline__ void wait_vmem_all()
     __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
 }
 
+// Workgroup barrier for the staged tiles: this wave's LDS stores complete
+// (lgkmcnt(0); its buffer-to-LDS copies were waited for by the caller), then
+// s_barrier, with compiler-only fences so no LDS access moves across it.  A
+// __syncthreads() would also wait for every global store in flight, which
+// here are the last pass's output stores.
+__device__ __forceinline__ void barrier_lds()
+{
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));  // lgkmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// s_waitcnt vmcnt(kRows3): all but the last kRows3 vector-memory operations of
+// this wave complete (they complete in issue order).
+__device__ __forceinline__ void wait_vmem_but_rows()
+{
+    static_assert(kRows3 < 16, "vmcnt low field");
+    __builtin_amdgcn_s_waitcnt(kRows3 | (7 << 4) | (15 << 8));
+}
+
 __device__ __forceinline__ float2 c_add(float2 a, float2 b)
 {
     return make_float2(a.x + b.x, a.y + b.y);
@@ -174,6 +195,12 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const in
             if constexpr (b != 0) v[i & 1][2 * q + 1] = row[-b];
         });
     };
+    // Taps of the first output row, requested before the 2M rows of pair sums
+    // that precede it, so their latency hides behind those rows.
+    if (__builtin_amdgcn_ballot_w64(jrow[0] != jcur) != 0) {
+        load_pass_taps<M, LO, HI>(h, rt, jrow[0]);
+        jcur = jrow[0];
+    }
     fetch(std::integral_constant<int, 0>{});
     static_for<0, NR>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -255,7 +282,8 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // loads (no registers on the way): each wave copies its rows, a row being
 // the 2 (64 + 2M) dwords of columns y0 - M .. y0 + 63 + M, 64 dwords per
 // instruction.  Rows outside [0, nx) lie outside the buffer and arrive as
-// zeros; columns outside [0, ny) are cleared afterwards (fix_edges).
+// zeros; so do columns outside [0, ny), whose lanes read at an offset pushed
+// out of range (the same for every row).
 template <int M>
 __device__ __forceinline__ void stage_rows(float2* Tb, __amdgpu_buffer_rsrc_t rp, int x0, int y0,
                                            int ny, int wave, int lane)
@@ -269,31 +297,24 @@ __device__ __forceinline__ void stage_rows(float2* Tb, __amdgpu_buffer_rsrc_t rp
     // instruction's immediate offset, which applies to the global and the LDS
     // address alike (so the LDS base stays at the row start).
     const int lane4 = lane * 4;
+    constexpr int NCH = (DW + 63) / 64;
+    int bias[NCH];
+    static_for<0, NCH>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int yc = y0 - M + (i * 64 + lane) / 2;  // column of this lane's dword
+        bias[i] = (unsigned)yc < (unsigned)ny ? 0 : 0x40000000;
+    });
 #pragma unroll
     for (int q = 0; q < HP / kWaves3; ++q) {
         const int r = q * kWaves3 + wave;
         const int voff = ((x0 - M + r) * ny + (y0 - M)) * 8 + lane4;
         char* dst = reinterpret_cast<char*>(Tb + r * W);
-        static_for<0, (DW + 63) / 64>([&](auto I) {
+        static_for<0, NCH>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if (i * 64 + lane < DW)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rp, (lds_ptr_t)dst, 4, voff, 0, i * 256, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rp, (lds_ptr_t)dst, 4, voff + bias[i], 0,
+                                                         i * 256, 0);
         });
-    }
-}
-
-// Zero the staged columns that lie outside [0, ny): [0, cl) and [ch, W).
-template <int M>
-__device__ __forceinline__ void fix_edges(float2* Tb, int cl, int ch)
-{
-    constexpr int W = kLanes3 + 2 * M;
-    constexpr int H = kTileX3 + 2 * M;
-    const int hi0 = ch > cl ? ch : cl;
-    const int nc = cl + (W > hi0 ? W - hi0 : 0);
-    for (int e = threadIdx.x; e < H * nc; e += kThreads3) {
-        const int r = e / nc, k = e % nc;
-        const int c = k < cl ? k : hi0 + (k - cl);
-        Tb[r * W + c] = make_float2(0.0f, 0.0f);
     }
 }
 
@@ -336,10 +357,6 @@ k_step3d(Step3dArgs A)
     // past nx land past the plane's end by themselves; a column past ny is
     // moved out of range as a whole (stores out of range are dropped).
     const int qbase = y < A.ny ? (x0 + r0) * ny8 + y * 8 : 0x40000000;
-    // staged columns outside the volume: [0, cl) and [ch, W)
-    const int cl = M - y0 > 0 ? M - y0 : 0;
-    const int ch = A.ny - (y0 - M);
-    const bool edge = cl > 0 || ch < W;
     const int pbytes = (int)(plane * sizeof(float2));
 
     const int wbeg = g * A.wpg;
@@ -352,13 +369,15 @@ k_step3d(Step3dArgs A)
         const int cur = (w - wbeg) & 1;
         float2* Tb = T[cur];
         // This wave's copies into Tb are complete; after the barrier so are
-        // every wave's, and nobody reads the other buffer any more.
-        wait_vmem_all();
-        __syncthreads();
-        if (edge) {
-            fix_edges<M>(Tb, cl, ch);
-            __syncthreads();
-        }
+        // every wave's, and nobody reads the other buffer any more.  After
+        // the first frequency, the copies were followed by the kRows3 output
+        // stores of the last pass (one per row, unconditional), which need
+        // not have completed.
+        if (w == wbeg)
+            wait_vmem_all();
+        else
+            wait_vmem_but_rows();
+        barrier_lds();
         const double ar = om / A.dk;
         if (w + 1 < wend) om = A.omega[w + 1];
         int jrow[kRows3];
