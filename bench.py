@@ -48,8 +48,8 @@ METRIC = "f-x extrapolation G complex tap-MAC/s + image err vs FP64; batched/adj
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle legs (no image error, no cpu_baseline)")
     ap.add_argument("--no-extras", action="store_true",
