@@ -26,7 +26,10 @@ Extras on the same line (each against the plain per-section GPU path):
              migration (10 iterations, 5 % noise);
   volume3d - the 3-D extension on a 256 x 256 x 200 volume with 128
              frequencies and 11 x 11 circularly symmetric extrapolators,
-             with the FP64 oracle timed on its first depth steps.
+             with the FP64 oracle timed on its first depth steps;
+  transform - the transform along t of a 1024 x 1024 t-x section to the 200
+             migration frequencies on the matrix cores, with the FP64 oracle
+             timed on a sample of traces.
 """
 from __future__ import annotations
 
@@ -57,7 +60,7 @@ def parse():
     ap.add_argument("--traffic", default=None,
                     help="JSON file with rocprofv3-derived HBM bytes per launch "
                          "(default profiles/traffic.json)")
-    ap.add_argument("--profile", choices=["plain", "batched", "adjoint", "volume3d"],
+    ap.add_argument("--profile", choices=["plain", "batched", "adjoint", "volume3d", "transform"],
                     default=None,
                     help="short run of one part for profilers: warmup + steps, no oracle, "
                          "prints timings only")
@@ -295,6 +298,8 @@ def batched(torch, mig, synth, dev, args, profile=False):
     torch.cuda.synchronize()
     same = all(torch.equal(b["image"], o) for b, o in zip(batch, outs))
     tap_macs = sum(s.nx * s.nw * (s.nz - 1) * desc.ntaps for s in secs)
+    M = (desc.ntaps - 1) // 2
+    flop = sum(s.nx * s.nw * (s.nz - 1) for s in secs) * (8 * (M + 1) + 2 * M)
     out = {
         "workload": "64 sections, seed-drawn nx 256-2048, nz 200-800, nw 100-300, 35-tap "
                     "table, seed 3",
@@ -306,6 +311,16 @@ def batched(torch, mig, synth, dev, args, profile=False):
         "tune": best,
         "tune_candidates": len(table),
         "images_bit_identical_to_plain": bool(same),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "the batched launches (one per kernel variant) with their small "
+                      "pre-kernels, folded Eq. 1 FLOP of every section",
+            "achieved": round(flop / (ms_b * 1e-3) / 1e12, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(flop / (ms_b * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "traffic": None,
+        },
     }
     print("batched: %.3f ms vs plain %.3f ms (%s)" % (ms_b, ms_p, best), file=sys.stderr,
           flush=True)
@@ -359,6 +374,10 @@ def adjoint(torch, mig, synth, dev, args, ctx=None, profile=False):
     with Timer(torch) as t:
         m, hist = lsm.cgls(d_obs, vel, omega, tab["tab32"], desc, niter=10)
     err = float(torch.linalg.norm(m - refl) / torch.linalg.norm(refl))
+    # per point and step: (M+1) products conj(h) q (6 FLOP) and 2M complex
+    # additions of the gather (4M FLOP)
+    M = (desc.ntaps - 1) // 2
+    flop_adj = nx * sec.nw * (nz - 1) * (6 * (M + 1) + 4 * M)
     out = {
         "workload": "adjoint of the headline section's migration (reflectivity -> data), "
                     "and CGLS least-squares migration with 5 % Gaussian noise, 10 iterations",
@@ -369,6 +388,17 @@ def adjoint(torch, mig, synth, dev, args, ctx=None, profile=False):
         "cgls_ms_total": round(t.ms, 2),
         "cgls_residual_history": [round(h, 4) for h in hist],
         "cgls_model_rel_err": round(err, 4),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "demigration launch (register-tap adjoint kernel, all depth steps) with "
+                      "its slowness pre-kernel",
+            "achieved": round(flop_adj / (ms_adj * 1e-3) / 1e12, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(flop_adj / (ms_adj * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "flop_per_output": 6 * (M + 1) + 4 * M,
+            "traffic": None,
+        },
     }
     print("adjoint: %.3f ms vs migrate %.3f ms; CGLS %.1f ms" % (ms_adj, ms_fwd, t.ms),
           file=sys.stderr, flush=True)
@@ -459,11 +489,68 @@ def volume3d(torch, mig, synth, dev, args, profile=False):
     return out
 
 
+# --------------------------------------------------------------------------- #
+# Transform along t (Algorithm 1, first step) on the matrix cores.
+# --------------------------------------------------------------------------- #
+def transform(torch, mig, synth, dev, args, profile=False):
+    nx, nt, dt = 1024, 1024, 0.004
+    om = synth.omegas(200, 5.0, 55.0)
+    nw = om.size
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal((nx, nt)).astype(np.float32)
+    sec = torch.from_numpy(p).to(dev)
+    omega = torch.from_numpy(om).to(dev)
+    out = torch.empty((nx, nw), dtype=torch.complex64, device=dev)
+    ws = torch.empty(max(mig.transform_workspace_size(nt, nw), 1), dtype=torch.uint8,
+                     device=dev)
+    reps = max(1, args.steps)
+    ms = timed(torch, lambda: mig.transform_t(sec, dt, omega, out=out, ws=ws), reps)
+    if profile:
+        print(json.dumps({"part": "transform", "ms": ms}))
+        return None
+    flop = 2.0 * nx * nt * 2 * nw      # real [nx][nt] x [nt][2 nw]
+    res = {
+        "workload": "t-x section nx=1024, nt=1024, dt=4 ms (seeded Gaussian samples) to the "
+                    "200 migration frequencies 5-55 Hz: DFT matrix built in FP64, product on "
+                    "FP32 MFMA",
+        "ms": round(ms, 4),
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "mig_transform_t: DFT-matrix kernel + v_mfma_f32_16x16x4f32 product",
+            "achieved": round(flop / (ms * 1e-3) / 1e12, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(flop / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "flop_per_launch": flop,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 64                               # sampled traces
+        t0 = time.time()
+        ref = oracle.transform_t(p[:k], dt, om)
+        t_or = time.time() - t0
+        got = out[:k].cpu().numpy()
+        res["rel_l2_vs_fp64_sample"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res["cpu_baseline"] = {
+            "value": round(2.0 * k * nt * 2 * nw / t_or / 1e9, 3),
+            "unit": "GFLOP/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "the first %d of the 1024 traces (FP64 direct DFT)" % k,
+            "seconds": round(t_or, 4),
+        }
+    print("transform: %.4f ms (%.1f TFLOP/s)" % (ms, res["roofline"]["achieved"]),
+          file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU; runs over several GPUs are not supported "
               "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
@@ -482,6 +569,9 @@ def main():
     if args.profile == "volume3d":
         volume3d(torch, mig, synth, dev, args, profile=True)
         return
+    if args.profile == "transform":
+        transform(torch, mig, synth, dev, args, profile=True)
+        return
     if args.profile == "plain":
         args.no_cpu_baseline = True
     res, ctx = headline(torch, mig, synth, dev, args)
@@ -493,6 +583,7 @@ def main():
         res["batched"] = batched(torch, mig, synth, dev, args)
         res["adjoint"] = adjoint(torch, mig, synth, dev, args, ctx)
         res["volume3d"] = volume3d(torch, mig, synth, dev, args)
+        res["transform"] = transform(torch, mig, synth, dev, args)
     print(json.dumps(res), flush=True)
 
 

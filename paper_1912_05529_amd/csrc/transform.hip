@@ -8,9 +8,8 @@
 // whose row-major result is exactly the interleaved complex64 plane [nx][nw].
 // B is built once per call in FP64 (phases up to thousands of radians) and
 // rounded to FP32; the product runs on the matrix cores with
-// v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate): 64 x 64 output tiles per
-// 256-thread workgroup, each wavefront a 32 x 32 quadrant (2 x 2 MFMA tiles),
-// K staged through LDS 16 at a time with zero padding at the ragged edges.
+// v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate), one wavefront per 32 x 32
+// output block.
 #include "common.hpp"
 
 namespace mig {
@@ -18,8 +17,6 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64;
-constexpr int kK = 16;
 
 __global__ void k_dft_matrix(const double* __restrict__ omega, int nw, int nt, double dt,
                              float* __restrict__ B)
@@ -35,62 +32,256 @@ __global__ void k_dft_matrix(const double* __restrict__ omega, int nw, int nt, d
     }
 }
 
-// MFMA 16x16x4 operand layout (lane l of a wavefront): A element
-// (row l % 16, k l / 16), B element (k l / 16, column l % 16); result lane l
-// holds D[4 (l / 16) + v][l % 16], v = 0..3.
-__global__ void __launch_bounds__(256) k_gemm_mfma(const float* __restrict__ A,
-                                                   const float* __restrict__ B,
-                                                   float* __restrict__ C, int M, int N, int K)
+// One wavefront per 32 x 32 block of C (2 x 2 tiles of v_mfma_f32_16x16x4f32),
+// operands read straight from global memory (L2-resident: A and B together are
+// a few MB), no LDS and no barriers.  The order of the k terms inside a sum is
+// free, so in step j of a 16-wide chunk lane group g = lane / 16 supplies
+// k = 4g + j: each lane then reads 4 consecutive k of its A row as one 16-byte
+// load, and each B row is read by 16 consecutive lanes.  Chunks of 32 k are
+// triple-buffered in registers: a chunk's loads are issued three chunks (96
+// MFMAs, about 1.4 us) before its MFMAs, which covers the L2 latency with the
+// one wavefront per SIMD the grid provides.
+//
+// MFMA 16x16x4 layout (lane l): A element (row l % 16, k-slot l / 16), B
+// element (k-slot l / 16, column l % 16); result lane l holds
+// D[4 (l / 16) + v][l % 16], v = 0..3.
+//
+// Ragged edges: rows of A past M and columns of B past N are read at the last
+// valid row / column (they only feed outputs that are not stored); k past K
+// reads row K-1 of B and a zero from A, so it adds nothing.
+constexpr int kBlk = 32;   // output block per wavefront
+constexpr int kKc = 32;    // k per chunk
+
+struct GemmChunk {
+    f32x4 a[2][2];   // [row tile][half of the chunk]: k = k0 + 16 h + 4 g + 0..3
+    float b[2][8];   // [column tile][4 h + j]:        k = k0 + 16 h + 4 g + j
+};
+
+// Branch-free loads (the same number of load instructions on every path, so
+// the waits stay one chunk-set deep).  VEC (K a multiple of 4): k and K are
+// both multiples of 4, so a 16-byte group is wholly inside or wholly past K; it
+// is read at a valid address and zeroed past K.
+template <bool VEC>
+__device__ __forceinline__ void load_chunk(GemmChunk& c, const float* __restrict__ A,
+                                           const float* __restrict__ B, int M, int N, int K,
+                                           int row0, int col0, int k0, int lane)
 {
-    __shared__ float As[kTile][kK + 1];
-    __shared__ float Bs[kK][kTile + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int row0 = blockIdx.y * kTile, col0 = blockIdx.x * kTile;
+    const int g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int r = min(row0 + 16 * i + l16, M - 1);
+        const float* ar = A + (size_t)r * K;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = k0 + 16 * h + 4 * g;
+            f32x4 v;
+            if constexpr (VEC) {
+                v = *reinterpret_cast<const f32x4*>(ar + min(k, K - 4));
+                if (k >= K) v = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float x = ar[min(k + e, K - 1)];
+                    v[e] = k + e < K ? x : 0.0f;
+                }
+            }
+            c.a[i][h] = v;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int col = min(col0 + 16 * t + l16, N - 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = min(k0 + 16 * h + 4 * g + j, K - 1);
+                c.b[t][4 * h + j] = B[(size_t)k * N + col];
+            }
+    }
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(64) k_gemm_mfma(const float* __restrict__ A,
+                                                  const float* __restrict__ B,
+                                                  float* __restrict__ C, int M, int N, int K)
+{
+    const int lane = threadIdx.x;
+    const int row0 = blockIdx.y * kBlk, col0 = blockIdx.x * kBlk;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < 2; ++t) acc[i][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < K; k0 += kK) {
-        for (int e = threadIdx.x; e < kTile * kK; e += blockDim.x) {
-            const int r = e / kK, c = e % kK;
-            const int gr = row0 + r, gc = k0 + c;
-            As[r][c] = (gr < M && gc < K) ? A[(size_t)gr * K + gc] : 0.0f;
-        }
-        for (int e = threadIdx.x; e < kK * kTile; e += blockDim.x) {
-            const int r = e / kTile, c = e % kTile;
-            const int gr = k0 + r, gc = col0 + c;
-            Bs[r][c] = (gr < K && gc < N) ? B[(size_t)gr * N + gc] : 0.0f;
-        }
-        __syncthreads();
+    auto mma = [&](const GemmChunk& c) {
 #pragma unroll
-        for (int kk = 0; kk < kK; kk += 4) {
-            const int k = kk + (lane >> 4);
-            float a[2], b[2];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[wr * 32 + i * 16 + (lane & 15)][k];
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[k][wc * 32 + j * 16 + (lane & 15)];
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();
+                    for (int t = 0; t < 2; ++t)
+                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            c.a[i][h][j], c.b[t][4 * h + j], acc[i][t], 0, 0, 0);
+    };
+    // Loads are issued unconditionally (chunks past the end re-read the last
+    // one), so every chunk waits for exactly its own loads.
+    const int nch = (K + kKc - 1) / kKc;
+    auto at = [&](int c) { return (c < nch ? c : nch - 1) * kKc; };
+    GemmChunk c0, c1, c2;
+    load_chunk<VEC>(c0, A, B, M, N, K, row0, col0, at(0), lane);
+    load_chunk<VEC>(c1, A, B, M, N, K, row0, col0, at(1), lane);
+    load_chunk<VEC>(c2, A, B, M, N, K, row0, col0, at(2), lane);
+    for (int c = 0; c < nch; c += 3) {
+        mma(c0);
+        load_chunk<VEC>(c0, A, B, M, N, K, row0, col0, at(c + 3), lane);
+        if (c + 1 >= nch) break;
+        mma(c1);
+        load_chunk<VEC>(c1, A, B, M, N, K, row0, col0, at(c + 4), lane);
+        if (c + 2 >= nch) break;
+        mma(c2);
+        load_chunk<VEC>(c2, A, B, M, N, K, row0, col0, at(c + 5), lane);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v;
-                const int c = col0 + wc * 32 + j * 16 + (lane & 15);
-                if (r < M && c < N) C[(size_t)r * N + c] = acc[i][j][v];
+                const int r = row0 + 16 * i + 4 * (lane >> 4) + v;
+                const int c = col0 + 16 * t + (lane & 15);
+                if (r < M && c < N) C[(size_t)r * N + c] = acc[i][t][v];
             }
+}
+
+// Main kernel: 64 x 32 output block per 256-thread workgroup, each wave a
+// 16 x 32 strip (1 x 2 MFMA tiles), so that the grid spreads over every CU;
+// k in chunks of 32 copied global -> LDS by buffer-to-LDS loads (no registers
+// on the way), four chunk buffers in flight: chunk c+3 is requested while
+// chunk c is multiplied.  Elements past the ragged edges (rows >= M, columns
+// >= N, k >= K) are read at an offset pushed out of the buffer's range and
+// arrive as zeros.  Used when every offset fits in 30 bits.
+//
+// LDS: A chunk [64 rows][32 k], the 16-byte k-groups of row r stored at slot
+// group ^ (r & 7), so that the eight rows a 16-byte MFMA-operand read touches
+// per cycle land on different banks; B chunk [32 k][32 columns].
+constexpr int kGM = 64;          // output rows per workgroup
+constexpr int kGN = 32;          // output columns per workgroup
+constexpr int kGK = 32;          // k per chunk
+constexpr int kGChunkF = kGM * kGK + kGK * kGN;   // floats per chunk buffer (A then B)
+constexpr int kGBuf = 4;         // chunk buffers
+constexpr int kGCopies = 12;     // copy instructions per wave per chunk (8 A + 4 B)
+constexpr int kOOR = 0x40000000; // byte offset past any buffer this kernel reads
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+constexpr int kRawWord3 = 0x00020000;
+
+__device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc_t ra,
+                                                __amdgpu_buffer_rsrc_t rb, int M, int N, int K,
+                                                int row0, int col0, int k0, int wave, int lane)
+{
+    const int half = lane >> 5, p = lane & 31;
+    // A: wave w copies rows 16w .. 16w+15, two rows per instruction
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = 16 * wave + 2 * q + half;
+        const int k = k0 + 4 * ((p >> 2) ^ (r & 7)) + (p & 3);
+        const int gr = row0 + r;
+        const int off = (gr < M && k < K) ? (gr * K + k) * 4 : kOOR;
+        float* dst = buf + (16 * wave + 2 * q) * kGK;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)dst, 4, off, 0, 0, 0);
+    }
+    // B: wave w copies k rows 8w .. 8w+7, two rows of 32 columns per instruction
+    float* bb = buf + kGM * kGK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int kr = 8 * wave + 2 * q + half;
+        const int k = k0 + kr, c = col0 + p;
+        const int off = (k < K && c < N) ? (k * N + c) * 4 : kOOR;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)(bb + (8 * wave + 2 * q) * kGN), 4,
+                                                 off, 0, 0, 0);
+    }
+}
+
+// vmcnt(2 kGCopies): all but this wave's copies of the two newest chunks are
+// complete (vmcnt[3:0] | vmcnt[5:4] in bits 15:14).
+__device__ __forceinline__ void wait_all_but_two_chunks()
+{
+    constexpr int n = 2 * kGCopies;
+    static_assert(n < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
+__device__ __forceinline__ void barrier_lds()
+{
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));  // lgkmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
+                                                  const float* __restrict__ B,
+                                                  float* __restrict__ C, int M, int N, int K)
+{
+    __shared__ float buf[kGBuf][kGChunkF];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int row0 = blockIdx.y * kGM, col0 = blockIdx.x * kGN;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc((void*)A, 0, M * K * 4, kRawWord3);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void*)B, 0, K * N * 4, kRawWord3);
+    const int g = lane >> 4, l16 = lane & 15;
+    f32x4 acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // Chunk copies are issued unconditionally (chunks past the end read only
+    // out-of-range offsets, i.e. zeros, into a buffer nobody reads), so that
+    // exactly 2 kGCopies copies are always newer than those of the chunk in
+    // use.
+    const int nch = (K + kGK - 1) / kGK;
+#pragma unroll
+    for (int q = 0; q < kGBuf - 1; ++q)
+        gemm_copy_chunk(buf[q], ra, rb, M, N, K, row0, col0, q * kGK, wave, lane);
+    const int r = 16 * wave + l16;   // this lane's A row in the block
+    for (int c = 0; c < nch; ++c) {
+        // this wave's copies of chunk c are in; after the barrier every wave's
+        // are, and every wave is done with chunk c-1, whose buffer takes
+        // chunk c+3
+        wait_all_but_two_chunks();
+        barrier_lds();
+        gemm_copy_chunk(buf[(c + kGBuf - 1) % kGBuf], ra, rb, M, N, K, row0, col0,
+                        (c + kGBuf - 1) * kGK, wave, lane);
+        const float* a = buf[c % kGBuf];
+        const float* b = a + kGM * kGK;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 av = *reinterpret_cast<const f32x4*>(a + r * kGK + 4 * ((4 * h + g) ^ (r & 7)));
+            float bv[2][4];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bv[t][j] = b[(16 * h + 4 * g + j) * kGN + 16 * t + l16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[t][j], acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = row0 + 16 * wave + 4 * g + v;
+            const int cc = col0 + 16 * t + l16;
+            if (rr < M && cc < N) C[(size_t)rr * N + cc] = acc[t][v];
+        }
 }
 
 }  // namespace
@@ -104,9 +295,20 @@ int launch_transform(const float* section, int nx, int nt, double dt, const doub
     hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)blocks), dim3(256), 0, s, omega, nw, nt, dt, B);
     if (hipGetLastError() != hipSuccess) return MIG_E_DEVICE;
     const int N = 2 * nw;
-    dim3 grid((N + kTile - 1) / kTile, (nx + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, section, B,
-                       reinterpret_cast<float*>(out), nx, N, nt);
+    // 30-bit byte offsets on the LDS path (the out-of-range marker is 2^30)
+    if ((size_t)nx * nt * 4 < (size_t)kOOR && (size_t)nt * N * 4 < (size_t)kOOR) {
+        dim3 g2((N + kGN - 1) / kGN, (nx + kGM - 1) / kGM);
+        hipLaunchKernelGGL(k_gemm_lds, g2, dim3(256), 0, s, section, B,
+                           reinterpret_cast<float*>(out), nx, N, nt);
+        return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+    }
+    dim3 grid((N + kBlk - 1) / kBlk, (nx + kBlk - 1) / kBlk);
+    if ((nt & 3) == 0)  // rows of the section 16-byte aligned
+        hipLaunchKernelGGL(k_gemm_mfma<true>, grid, dim3(64), 0, s, section, B,
+                           reinterpret_cast<float*>(out), nx, N, nt);
+    else
+        hipLaunchKernelGGL(k_gemm_mfma<false>, grid, dim3(64), 0, s, section, B,
+                           reinterpret_cast<float*>(out), nx, N, nt);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 

@@ -343,6 +343,11 @@ def demigrate(image, vel, omega, tab32, desc, nw=None, out=None, ws=None):
     return out
 
 
+def transform_workspace_size(nt, nw) -> int:
+    """Bytes of workspace mig_transform_t needs (the FP32 DFT matrix)."""
+    return int(lib().mig_transform_workspace_size(int(nt), int(nw)))
+
+
 def transform_t(section, dt, omega, out=None, ws=None):
     """Transform along t: section [nx][nt] float32 -> plane [nx][nw] complex64."""
     nx, nt = section.shape
