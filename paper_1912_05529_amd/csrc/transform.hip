@@ -158,58 +158,92 @@ __global__ void __launch_bounds__(64) k_gemm_mfma(const float* __restrict__ A,
 
 // Main kernel: 64 x 32 output block per 256-thread workgroup, each wave a
 // 16 x 32 strip (1 x 2 MFMA tiles), so that the grid spreads over every CU;
-// k in chunks of 32 copied global -> LDS by buffer-to-LDS loads (no registers
+// k in chunks of 64 copied global -> LDS by buffer-to-LDS loads (no registers
 // on the way), four chunk buffers in flight: chunk c+3 is requested while
 // chunk c is multiplied.  Elements past the ragged edges (rows >= M, columns
 // >= N, k >= K) are read at an offset pushed out of the buffer's range and
 // arrive as zeros.  Used when every offset fits in 30 bits.
 //
-// LDS: A chunk [64 rows][32 k], the 16-byte k-groups of row r stored at slot
+// LDS: A chunk [64 rows][64 k], the 16-byte k-groups of row r stored at slot
 // group ^ (r & 7), so that the eight rows a 16-byte MFMA-operand read touches
-// per cycle land on different banks; B chunk [32 k][32 columns].
+// per cycle land on different banks; B chunk [64 k][32 columns], column c of
+// k row kr stored at c ^ 16 ((kr >> 2) & 1), so that the 32 lanes of a B-operand
+// read (k rows 4 apart) cover all 32 banks.
 constexpr int kGM = 64;          // output rows per workgroup
 constexpr int kGN = 32;          // output columns per workgroup
-constexpr int kGK = 32;          // k per chunk
+constexpr int kGK = 64;          // k per chunk
 constexpr int kGChunkF = kGM * kGK + kGK * kGN;   // floats per chunk buffer (A then B)
 constexpr int kGBuf = 4;         // chunk buffers
-constexpr int kGCopies = 12;     // copy instructions per wave per chunk (8 A + 4 B)
 constexpr int kOOR = 0x40000000; // byte offset past any buffer this kernel reads
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 constexpr int kRawWord3 = 0x00020000;
 
+// Copy instructions per wave per chunk: 16-byte copies (X4, K and N multiples of
+// 4: every 4-float group wholly inside or wholly past the edges) or 4-byte ones.
+template <bool X4>
+constexpr int gemm_copies() { return X4 ? 6 : 24; }
+
+template <bool X4>
 __device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc_t ra,
                                                 __amdgpu_buffer_rsrc_t rb, int M, int N, int K,
                                                 int row0, int col0, int k0, int wave, int lane)
 {
-    const int half = lane >> 5, p = lane & 31;
-    // A: wave w copies rows 16w .. 16w+15, two rows per instruction
+    static_assert(kGK == 64 && kGM == 64 && kGN == 32, "copy pattern");
+    float* bb = buf + kGM * kGK;
+    if constexpr (X4) {
+        // A: wave w copies rows 16w .. 16w+15, four rows (16 groups each) per
+        // instruction
+        const int s16 = lane & 15, r4 = lane >> 4;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int r = 16 * wave + 2 * q + half;
-        const int k = k0 + 4 * ((p >> 2) ^ (r & 7)) + (p & 3);
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * wave + 4 * q + r4;
+            const int k = k0 + 4 * (s16 ^ (r & 7));
+            const int gr = row0 + r;
+            const int off = (gr < M && k < K) ? (gr * K + k) * 4 : kOOR;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)(buf + (16 * wave + 4 * q) * kGK),
+                                                     16, off, 0, 0, 0);
+        }
+        // B: wave w copies k rows 16w .. 16w+15, eight rows per instruction
+        const int s8 = lane & 7, r8 = lane >> 3;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kr = 16 * wave + 8 * q + r8;
+            const int k = k0 + kr, c = col0 + 4 * (s8 ^ (((kr >> 2) & 1) << 2));
+            const int off = (k < K && c < N) ? (k * N + c) * 4 : kOOR;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)(bb + (16 * wave + 8 * q) * kGN),
+                                                     16, off, 0, 0, 0);
+        }
+        return;
+    }
+    // A: wave w copies rows 16w .. 16w+15, one row per instruction
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = 16 * wave + q;
+        const int k = k0 + 4 * ((lane >> 2) ^ (r & 7)) + (lane & 3);
         const int gr = row0 + r;
         const int off = (gr < M && k < K) ? (gr * K + k) * 4 : kOOR;
-        float* dst = buf + (16 * wave + 2 * q) * kGK;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)dst, 4, off, 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)(buf + r * kGK), 4, off, 0, 0, 0);
     }
-    // B: wave w copies k rows 8w .. 8w+7, two rows of 32 columns per instruction
-    float* bb = buf + kGM * kGK;
+    // B: wave w copies k rows 16w .. 16w+15, two rows of 32 columns per
+    // instruction
+    const int half = lane >> 5, p = lane & 31;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int kr = 8 * wave + 2 * q + half;
-        const int k = k0 + kr, c = col0 + p;
+    for (int q = 0; q < 8; ++q) {
+        const int kr = 16 * wave + 2 * q + half;
+        const int k = k0 + kr, c = col0 + (p ^ (((kr >> 2) & 1) << 4));
         const int off = (k < K && c < N) ? (k * N + c) * 4 : kOOR;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)(bb + (8 * wave + 2 * q) * kGN), 4,
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)(bb + (16 * wave + 2 * q) * kGN), 4,
                                                  off, 0, 0, 0);
     }
 }
 
-// vmcnt(2 kGCopies): all but this wave's copies of the two newest chunks are
+// vmcnt(2 copies): all but this wave's copies of the two newest chunks are
 // complete (vmcnt[3:0] | vmcnt[5:4] in bits 15:14).
+template <bool X4>
 __device__ __forceinline__ void wait_all_but_two_chunks()
 {
-    constexpr int n = 2 * kGCopies;
+    constexpr int n = 2 * gemm_copies<X4>();
     static_assert(n < 64, "vmcnt field");
     __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
 }
@@ -222,6 +256,7 @@ __device__ __forceinline__ void barrier_lds()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+template <bool X4>
 __global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
                                                   const float* __restrict__ B,
                                                   float* __restrict__ C, int M, int N, int K)
@@ -241,32 +276,32 @@ __global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
 
     // Chunk copies are issued unconditionally (chunks past the end read only
     // out-of-range offsets, i.e. zeros, into a buffer nobody reads), so that
-    // exactly 2 kGCopies copies are always newer than those of the chunk in
+    // exactly two chunks' copies are always newer than those of the chunk in
     // use.
     const int nch = (K + kGK - 1) / kGK;
 #pragma unroll
     for (int q = 0; q < kGBuf - 1; ++q)
-        gemm_copy_chunk(buf[q], ra, rb, M, N, K, row0, col0, q * kGK, wave, lane);
+        gemm_copy_chunk<X4>(buf[q], ra, rb, M, N, K, row0, col0, q * kGK, wave, lane);
     const int r = 16 * wave + l16;   // this lane's A row in the block
     for (int c = 0; c < nch; ++c) {
         // this wave's copies of chunk c are in; after the barrier every wave's
         // are, and every wave is done with chunk c-1, whose buffer takes
         // chunk c+3
-        wait_all_but_two_chunks();
+        wait_all_but_two_chunks<X4>();
         barrier_lds();
-        gemm_copy_chunk(buf[(c + kGBuf - 1) % kGBuf], ra, rb, M, N, K, row0, col0,
+        gemm_copy_chunk<X4>(buf[(c + kGBuf - 1) % kGBuf], ra, rb, M, N, K, row0, col0,
                         (c + kGBuf - 1) * kGK, wave, lane);
         const float* a = buf[c % kGBuf];
         const float* b = a + kGM * kGK;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kGK / 16; ++h) {
             const f32x4 av = *reinterpret_cast<const f32x4*>(a + r * kGK + 4 * ((4 * h + g) ^ (r & 7)));
             float bv[2][4];
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    bv[t][j] = b[(16 * h + 4 * g + j) * kGN + 16 * t + l16];
+                    bv[t][j] = b[(16 * h + 4 * g + j) * kGN + ((16 * t + l16) ^ ((g & 1) << 4))];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -298,8 +333,12 @@ int launch_transform(const float* section, int nx, int nt, double dt, const doub
     // 30-bit byte offsets on the LDS path (the out-of-range marker is 2^30)
     if ((size_t)nx * nt * 4 < (size_t)kOOR && (size_t)nt * N * 4 < (size_t)kOOR) {
         dim3 g2((N + kGN - 1) / kGN, (nx + kGM - 1) / kGM);
-        hipLaunchKernelGGL(k_gemm_lds, g2, dim3(256), 0, s, section, B,
-                           reinterpret_cast<float*>(out), nx, N, nt);
+        if ((nt & 3) == 0 && (N & 3) == 0)
+            hipLaunchKernelGGL(k_gemm_lds<true>, g2, dim3(256), 0, s, section, B,
+                               reinterpret_cast<float*>(out), nx, N, nt);
+        else
+            hipLaunchKernelGGL(k_gemm_lds<false>, g2, dim3(256), 0, s, section, B,
+                               reinterpret_cast<float*>(out), nx, N, nt);
         return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
     }
     dim3 grid((N + kBlk - 1) / kBlk, (nx + kBlk - 1) / kBlk);
