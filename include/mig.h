@@ -10,11 +10,11 @@
  *     convolution of Eq. (1),
  *         P_{k+1}[x_i][r] = sum_{n=-M..M} h[n] P_k[x_{i-n}][r],  N = 2M+1,
  *     with a predesigned FIR extrapolator h chosen per point by the wavenumber
- *     omega_r / v(x_i, z_k) (Algorithm 1 "look-up table"; Sec. III: the cutoff
- *     varies from point to point);
+ *     omega_r / v(x_i, z_k) (the table look-up inside the loops of Algorithm 1;
+ *     Sec. III: the cutoff varies from point to point);
  *   - the image row of depth z_k is the sum of the plane over frequencies
- *     (Algorithm 1 "depth row by summing over frequencies"; Sec. III second
- *     kernel), taken here as Re sum_r P_k[x][r] (zero-time imaging).
+ *     (the imaging step of Algorithm 1; the second kernel of Sec. III), taken
+ *     here as Re sum_r P_k[x][r] (zero-time imaging).
  *
  * Conventions shared by every entry point
  *   - Every array argument is a DEVICE pointer owned by the caller (e.g. torch
@@ -66,6 +66,7 @@ enum {
 #define MIG_MAX_NTAPS 63     /* N odd, 1..63 (M = (N-1)/2 <= 31)              */
 #define MIG_MAX_NX 8192      /* lateral points per section                    */
 #define MIG_MAX_NW 1048576   /* frequencies per call                          */
+#define MIG_MAX_NT 4194304   /* time samples per trace (mig_transform_t)     */
 
 /*
  * Extrapolator-table descriptor.  Entry j (0 <= j < nk) is designed for the
@@ -130,8 +131,8 @@ MIG_API int mig_design_table(const mig_table_desc* d, mig_c128* tab64,
                              void* ws, size_t ws_bytes, void* stream);
 
 /*
- * A1 -- table look-up (Algorithm 1 "look-up table"; Sec. III filter chosen by
- * the wavenumber omega/v).  idx[row][x][r] = nearest entry j to
+ * A1 -- table look-up (the look-up step of Algorithm 1; Sec. III: the filter is
+ * chosen by the wavenumber omega/v).  idx[row][x][r] = nearest entry j to
  * omega_r / vel[row][x], computed as the IEEE-double sequence
  *     a = omega/dk; b = kmin/dk; s = 1/(double)v; t = a*s; t = t - b;
  *     u = t + 0.5;  j = 0 if !(u >= 1), nk-1 if u >= nk, else floor(u),
@@ -212,6 +213,7 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel,
  * the matrix cores in FP32 (the DFT matrix is formed in FP64 and rounded).
  *   section [nx][nt] float32 (in), omega [nw] float64 (in),
  *   out [nx][nw] complex64 (out), ws >= mig_transform_workspace_size bytes.
+ * nt <= MIG_MAX_NT (else MIG_E_ARG; the workspace query returns 0).
  */
 MIG_API size_t mig_transform_workspace_size(int32_t nt, int32_t nw);
 MIG_API int mig_transform_t(const float* section, int32_t nx, int32_t nt,

@@ -225,7 +225,7 @@ int orc_design_table(const orc_desc* d, int apply_scale, double* tab,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Table look-up (Algorithm 1: "look-up table" inside the space loop;       */
+/* Table look-up (the look-up inside the space loop of Algorithm 1;        */
 /* Sec. III: the cutoff depends on the wavenumber omega/v, which varies     */
 /* from point to point).  Nearest entry to k = omega/v on the uniform axis  */
 /* k_j = kmin + j dk, rounding halves up, clamped to [0, nk-1]; a velocity  */
@@ -261,7 +261,7 @@ int orc_table_index(const orc_desc* d, const double* omega, int32_t nw,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Imaging (Algorithm 1 "calculate depth row by summing over frequencies"; */
+/* Imaging (the depth-row step of Algorithm 1, a sum over frequencies;     */
 /* Sec. III second kernel): row[x] = sum_r Re P[x][r], r in order.          */
 /* ------------------------------------------------------------------------ */
 int orc_image(const double* plane, int32_t nx, int32_t nw, double* row)

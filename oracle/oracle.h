@@ -6,11 +6,10 @@
  * CPU-baseline leg of the benchmark may load it.  It shares no code, header,
  * table or constant with the HIP library, and it includes nothing from it.
  *
- * What it computes (paper: Shawahna, Salam & Al-Mouhamed, "Seismic Imaging:
- * An Overview and Parallel Implementation of Poststack Depth Migration"):
+ * What it computes (paper: Shawahna, Salam & Al-Mouhamed, arXiv 1912.05529):
  *   - orc_design_table : the predesigned 1-D complex FIR extrapolator bank
- *                        (Sec. II "design ... optimization problem", Sec. III
- *                        "design the filters in advance").  The paper gives no
+ *                        (Sec. II: the design is an optimization between two
+ *                        trade-offs; Sec. III: designed in advance).  The paper gives no
  *                        design method; this is a weighted least-squares fit to
  *                        the phase-shift operator with multiplicative
  *                        reweighting and a rigorous stability scale.
@@ -18,9 +17,8 @@
  *                        wavenumber omega/v, Sec. III).  Nearest entry.
  *   - orc_extrapolate  : Eq. (1), literally (unfolded sum over n), one depth
  *                        step after another (Algorithm 1 loops).
- *   - orc_image        : "depth row by summing over frequencies" (Algorithm 1,
- *                        Sec. III second kernel): real part of the sum over
- *                        omega.
+ *   - orc_image        : the depth row of Algorithm 1 (the second kernel of
+ *                        Sec. III): real part of the sum over omega.
  *   - orc_migrate      : Algorithm 1 end to end on an f-x section.
  *   - orc_demigrate    : the exact adjoint of orc_migrate (real inner product).
  *

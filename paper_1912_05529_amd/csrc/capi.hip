@@ -598,7 +598,7 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
 
 MIG_API size_t mig_transform_workspace_size(int32_t nt, int32_t nw)
 {
-    if (nt < 1 || nw < 1 || nw > MIG_MAX_NW) return 0;
+    if (nt < 1 || nt > MIG_MAX_NT || nw < 1 || nw > MIG_MAX_NW) return 0;
     return align_up((size_t)nt * 2 * nw * sizeof(float), kAlign);
 }
 
@@ -606,7 +606,8 @@ MIG_API int mig_transform_t(const float* section, int32_t nx, int32_t nt, double
                             const double* omega, int32_t nw, mig_c64* out, void* ws,
                             size_t ws_bytes, void* stream)
 {
-    if (!section || !omega || !out || !sizes_ok(nx, nw) || nt < 1 || !(dt > 0.0))
+    if (!section || !omega || !out || !sizes_ok(nx, nw) || nt < 1 || nt > MIG_MAX_NT ||
+        !(dt > 0.0))
         return MIG_E_ARG;
     const size_t need = mig_transform_workspace_size(nt, nw);
     if (!ws || ws_bytes < need) return MIG_E_WORKSPACE;

@@ -1,6 +1,6 @@
-// Transform along t of a zero-offset section (Algorithm 1, first step:
-// "Fourier transform ... along t-axis"), evaluated directly at the requested
-// frequencies:  P[x][r] = sum_n p[x][n] exp(-i omega_r n dt).
+// Transform along t of a zero-offset section (the first step of Algorithm 1),
+// evaluated directly at the requested frequencies:
+//     P[x][r] = sum_n p[x][n] exp(-i omega_r n dt).
 //
 // The frequencies need not be FFT bins, so this is a dense contraction
 //     C[nx][2 nw] = A[nx][nt] . B[nt][2 nw],
@@ -8,15 +8,13 @@
 // whose row-major result is exactly the interleaved complex64 plane [nx][nw].
 // B is built once per call in FP64 (phases up to thousands of radians) and
 // rounded to FP32; the product runs on the matrix cores with
-// v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate), one wavefront per 32 x 32
-// output block.
+// v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate).
 #include "common.hpp"
 
 namespace mig {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 
 __global__ void k_dft_matrix(const double* __restrict__ omega, int nw, int nt, double dt,
                              float* __restrict__ B)
@@ -32,137 +30,15 @@ __global__ void k_dft_matrix(const double* __restrict__ omega, int nw, int nt, d
     }
 }
 
-// One wavefront per 32 x 32 block of C (2 x 2 tiles of v_mfma_f32_16x16x4f32),
-// operands read straight from global memory (L2-resident: A and B together are
-// a few MB), no LDS and no barriers.  The order of the k terms inside a sum is
-// free, so in step j of a 16-wide chunk lane group g = lane / 16 supplies
-// k = 4g + j: each lane then reads 4 consecutive k of its A row as one 16-byte
-// load, and each B row is read by 16 consecutive lanes.  Chunks of 32 k are
-// triple-buffered in registers: a chunk's loads are issued three chunks (96
-// MFMAs, about 1.4 us) before its MFMAs, which covers the L2 latency with the
-// one wavefront per SIMD the grid provides.
-//
-// MFMA 16x16x4 layout (lane l): A element (row l % 16, k-slot l / 16), B
-// element (k-slot l / 16, column l % 16); result lane l holds
-// D[4 (l / 16) + v][l % 16], v = 0..3.
-//
-// Ragged edges: rows of A past M and columns of B past N are read at the last
-// valid row / column (they only feed outputs that are not stored); k past K
-// reads row K-1 of B and a zero from A, so it adds nothing.
-constexpr int kBlk = 32;   // output block per wavefront
-constexpr int kKc = 32;    // k per chunk
-
-struct GemmChunk {
-    f32x4 a[2][2];   // [row tile][half of the chunk]: k = k0 + 16 h + 4 g + 0..3
-    float b[2][8];   // [column tile][4 h + j]:        k = k0 + 16 h + 4 g + j
-};
-
-// Branch-free loads (the same number of load instructions on every path, so
-// the waits stay one chunk-set deep).  VEC (K a multiple of 4): k and K are
-// both multiples of 4, so a 16-byte group is wholly inside or wholly past K; it
-// is read at a valid address and zeroed past K.
-template <bool VEC>
-__device__ __forceinline__ void load_chunk(GemmChunk& c, const float* __restrict__ A,
-                                           const float* __restrict__ B, int M, int N, int K,
-                                           int row0, int col0, int k0, int lane)
-{
-    const int g = lane >> 4, l16 = lane & 15;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int r = min(row0 + 16 * i + l16, M - 1);
-        const float* ar = A + (size_t)r * K;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = k0 + 16 * h + 4 * g;
-            f32x4 v;
-            if constexpr (VEC) {
-                v = *reinterpret_cast<const f32x4*>(ar + min(k, K - 4));
-                if (k >= K) v = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float x = ar[min(k + e, K - 1)];
-                    v[e] = k + e < K ? x : 0.0f;
-                }
-            }
-            c.a[i][h] = v;
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int col = min(col0 + 16 * t + l16, N - 1);
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = min(k0 + 16 * h + 4 * g + j, K - 1);
-                c.b[t][4 * h + j] = B[(size_t)k * N + col];
-            }
-    }
-}
-
-template <bool VEC>
-__global__ void __launch_bounds__(64) k_gemm_mfma(const float* __restrict__ A,
-                                                  const float* __restrict__ B,
-                                                  float* __restrict__ C, int M, int N, int K)
-{
-    const int lane = threadIdx.x;
-    const int row0 = blockIdx.y * kBlk, col0 = blockIdx.x * kBlk;
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int t = 0; t < 2; ++t) acc[i][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-    auto mma = [&](const GemmChunk& c) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            c.a[i][h][j], c.b[t][4 * h + j], acc[i][t], 0, 0, 0);
-    };
-    // Loads are issued unconditionally (chunks past the end re-read the last
-    // one), so every chunk waits for exactly its own loads.
-    const int nch = (K + kKc - 1) / kKc;
-    auto at = [&](int c) { return (c < nch ? c : nch - 1) * kKc; };
-    GemmChunk c0, c1, c2;
-    load_chunk<VEC>(c0, A, B, M, N, K, row0, col0, at(0), lane);
-    load_chunk<VEC>(c1, A, B, M, N, K, row0, col0, at(1), lane);
-    load_chunk<VEC>(c2, A, B, M, N, K, row0, col0, at(2), lane);
-    for (int c = 0; c < nch; c += 3) {
-        mma(c0);
-        load_chunk<VEC>(c0, A, B, M, N, K, row0, col0, at(c + 3), lane);
-        if (c + 1 >= nch) break;
-        mma(c1);
-        load_chunk<VEC>(c1, A, B, M, N, K, row0, col0, at(c + 4), lane);
-        if (c + 2 >= nch) break;
-        mma(c2);
-        load_chunk<VEC>(c2, A, B, M, N, K, row0, col0, at(c + 5), lane);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = row0 + 16 * i + 4 * (lane >> 4) + v;
-                const int c = col0 + 16 * t + (lane & 15);
-                if (r < M && c < N) C[(size_t)r * N + c] = acc[i][t][v];
-            }
-}
-
 // Main kernel: 64 x 32 output block per 256-thread workgroup, each wave a
 // 16 x 32 strip (1 x 2 MFMA tiles), so that the grid spreads over every CU;
 // k in chunks of 64 copied global -> LDS by buffer-to-LDS loads (no registers
 // on the way), four chunk buffers in flight: chunk c+3 is requested while
 // chunk c is multiplied.  Elements past the ragged edges (rows >= M, columns
 // >= N, k >= K) are read at an offset pushed out of the buffer's range and
-// arrive as zeros.  Used when every offset fits in 30 bits.
+// arrive as zeros.  The buffer resources are rebased for every chunk at the
+// workgroup's first row and the chunk's first k, so offsets stay below 2^30
+// for nt <= MIG_MAX_NT and any nw <= MIG_MAX_NW.
 //
 // LDS: A chunk [64 rows][64 k], the 16-byte k-groups of row r stored at slot
 // group ^ (r & 7), so that the eight rows a 16-byte MFMA-operand read touches
@@ -184,12 +60,24 @@ constexpr int kRawWord3 = 0x00020000;
 template <bool X4>
 constexpr int gemm_copies() { return X4 ? 6 : 24; }
 
+// Resources for the chunk at k0: A from row row0, column k0; B from row k0,
+// column col0 (64-bit bases, so the 32-bit offsets stay small).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const float* base, size_t first,
+                                                             size_t total)
+{
+    const size_t left = total > first ? (total - first) * 4 : 0;
+    const int nrec = left < (size_t)kOOR ? (int)left : kOOR;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(base + first), 0, nrec, kRawWord3);
+}
+
 template <bool X4>
-__device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc_t ra,
-                                                __amdgpu_buffer_rsrc_t rb, int M, int N, int K,
+__device__ __forceinline__ void gemm_copy_chunk(float* buf, const float* __restrict__ A,
+                                                const float* __restrict__ B, int M, int N, int K,
                                                 int row0, int col0, int k0, int wave, int lane)
 {
     static_assert(kGK == 64 && kGM == 64 && kGN == 32, "copy pattern");
+    const __amdgpu_buffer_rsrc_t ra = chunk_rsrc(A, (size_t)row0 * K + k0, (size_t)M * K);
+    const __amdgpu_buffer_rsrc_t rb = chunk_rsrc(B, (size_t)k0 * N + col0, (size_t)K * N);
     float* bb = buf + kGM * kGK;
     if constexpr (X4) {
         // A: wave w copies rows 16w .. 16w+15, four rows (16 groups each) per
@@ -200,7 +88,7 @@ __device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc
             const int r = 16 * wave + 4 * q + r4;
             const int k = k0 + 4 * (s16 ^ (r & 7));
             const int gr = row0 + r;
-            const int off = (gr < M && k < K) ? (gr * K + k) * 4 : kOOR;
+            const int off = (gr < M && k < K) ? (r * K + (k - k0)) * 4 : kOOR;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)(buf + (16 * wave + 4 * q) * kGK),
                                                      16, off, 0, 0, 0);
         }
@@ -210,7 +98,7 @@ __device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc
         for (int q = 0; q < 2; ++q) {
             const int kr = 16 * wave + 8 * q + r8;
             const int k = k0 + kr, c = col0 + 4 * (s8 ^ (((kr >> 2) & 1) << 2));
-            const int off = (k < K && c < N) ? (k * N + c) * 4 : kOOR;
+            const int off = (k < K && c < N) ? (kr * N + (c - col0)) * 4 : kOOR;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)(bb + (16 * wave + 8 * q) * kGN),
                                                      16, off, 0, 0, 0);
         }
@@ -222,7 +110,7 @@ __device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc
         const int r = 16 * wave + q;
         const int k = k0 + 4 * ((lane >> 2) ^ (r & 7)) + (lane & 3);
         const int gr = row0 + r;
-        const int off = (gr < M && k < K) ? (gr * K + k) * 4 : kOOR;
+        const int off = (gr < M && k < K) ? (r * K + (k - k0)) * 4 : kOOR;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)(buf + r * kGK), 4, off, 0, 0, 0);
     }
     // B: wave w copies k rows 16w .. 16w+15, two rows of 32 columns per
@@ -232,7 +120,7 @@ __device__ __forceinline__ void gemm_copy_chunk(float* buf, __amdgpu_buffer_rsrc
     for (int q = 0; q < 8; ++q) {
         const int kr = 16 * wave + 2 * q + half;
         const int k = k0 + kr, c = col0 + (p ^ (((kr >> 2) & 1) << 4));
-        const int off = (k < K && c < N) ? (k * N + c) * 4 : kOOR;
+        const int off = (k < K && c < N) ? (kr * N + (c - col0)) * 4 : kOOR;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)(bb + (16 * wave + 2 * q) * kGN), 4,
                                                  off, 0, 0, 0);
     }
@@ -265,10 +153,6 @@ __global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int row0 = blockIdx.y * kGM, col0 = blockIdx.x * kGN;
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc((void*)A, 0, M * K * 4, kRawWord3);
-    const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc((void*)B, 0, K * N * 4, kRawWord3);
     const int g = lane >> 4, l16 = lane & 15;
     f32x4 acc[2];
 #pragma unroll
@@ -281,7 +165,7 @@ __global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
     const int nch = (K + kGK - 1) / kGK;
 #pragma unroll
     for (int q = 0; q < kGBuf - 1; ++q)
-        gemm_copy_chunk<X4>(buf[q], ra, rb, M, N, K, row0, col0, q * kGK, wave, lane);
+        gemm_copy_chunk<X4>(buf[q], A, B, M, N, K, row0, col0, q * kGK, wave, lane);
     const int r = 16 * wave + l16;   // this lane's A row in the block
     for (int c = 0; c < nch; ++c) {
         // this wave's copies of chunk c are in; after the barrier every wave's
@@ -289,7 +173,7 @@ __global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
         // chunk c+3
         wait_all_but_two_chunks<X4>();
         barrier_lds();
-        gemm_copy_chunk<X4>(buf[(c + kGBuf - 1) % kGBuf], ra, rb, M, N, K, row0, col0,
+        gemm_copy_chunk<X4>(buf[(c + kGBuf - 1) % kGBuf], A, B, M, N, K, row0, col0,
                         (c + kGBuf - 1) * kGK, wave, lane);
         const float* a = buf[c % kGBuf];
         const float* b = a + kGM * kGK;
@@ -330,23 +214,12 @@ int launch_transform(const float* section, int nx, int nt, double dt, const doub
     hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)blocks), dim3(256), 0, s, omega, nw, nt, dt, B);
     if (hipGetLastError() != hipSuccess) return MIG_E_DEVICE;
     const int N = 2 * nw;
-    // 30-bit byte offsets on the LDS path (the out-of-range marker is 2^30)
-    if ((size_t)nx * nt * 4 < (size_t)kOOR && (size_t)nt * N * 4 < (size_t)kOOR) {
-        dim3 g2((N + kGN - 1) / kGN, (nx + kGM - 1) / kGM);
-        if ((nt & 3) == 0 && (N & 3) == 0)
-            hipLaunchKernelGGL(k_gemm_lds<true>, g2, dim3(256), 0, s, section, B,
-                               reinterpret_cast<float*>(out), nx, N, nt);
-        else
-            hipLaunchKernelGGL(k_gemm_lds<false>, g2, dim3(256), 0, s, section, B,
-                               reinterpret_cast<float*>(out), nx, N, nt);
-        return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
-    }
-    dim3 grid((N + kBlk - 1) / kBlk, (nx + kBlk - 1) / kBlk);
-    if ((nt & 3) == 0)  // rows of the section 16-byte aligned
-        hipLaunchKernelGGL(k_gemm_mfma<true>, grid, dim3(64), 0, s, section, B,
+    dim3 grid((N + kGN - 1) / kGN, (nx + kGM - 1) / kGM);
+    if ((nt & 3) == 0 && (N & 3) == 0)  // every 4-float group wholly in or past the edges
+        hipLaunchKernelGGL(k_gemm_lds<true>, grid, dim3(256), 0, s, section, B,
                            reinterpret_cast<float*>(out), nx, N, nt);
     else
-        hipLaunchKernelGGL(k_gemm_mfma<false>, grid, dim3(64), 0, s, section, B,
+        hipLaunchKernelGGL(k_gemm_lds<false>, grid, dim3(256), 0, s, section, B,
                            reinterpret_cast<float*>(out), nx, N, nt);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }

@@ -91,6 +91,11 @@ def test_workspace_sizes_and_kernel_kinds(L):
     assert mig.kernel_kind(2049, 25) == 0
     assert mig.kernel_kind(512, 37) == 0
     assert mig.kernel_kind(512, 36) == -1
+    # transform along t: the FP32 DFT matrix [nt][2 nw], nt <= 2^22
+    assert mig.transform_workspace_size(1024, 200) == 1024 * 400 * 4
+    assert mig.transform_workspace_size(4194304, 1) == 4194304 * 2 * 4
+    assert mig.transform_workspace_size(4194305, 1) == 0
+    assert mig.transform_workspace_size(0, 1) == 0
 
 
 def test_3d_host_checks_and_workspace_sizes(L):

@@ -28,6 +28,21 @@ def test_transform_matches_oracle(nx, nt, nw):
     assert rel_l2(got.cpu().numpy(), ref) <= 1e-5
 
 
+@pytest.mark.parametrize("nx,nt,nw", [(2048, 131076, 8), (1024, 262147, 3)])
+def test_transform_large_sections_sampled(nx, nt, nw):
+    """Sections of over 2^30 bytes (the product's buffer offsets are taken from
+    per-chunk bases): sampled traces against the FP64 oracle, 16-byte copy path
+    (nt and 2 nw multiples of 4) and 4-byte copy path."""
+    print("large transform nx=%d nt=%d nw=%d" % (nx, nt, nw), flush=True)
+    rng = np.random.default_rng(nt)
+    p = rng.standard_normal((nx, nt), dtype=np.float32)
+    om = synth.omegas(nw, 5.0, 55.0)
+    got = mig.transform_t(torch.from_numpy(p).to(dev()), 0.001, torch.from_numpy(om).to(dev()))
+    idx = [0, 1, 777, nx - 1]
+    ref = oracle.transform_t(np.ascontiguousarray(p[idx]), 0.001, om)
+    assert rel_l2(got[idx].cpu().numpy(), ref) <= 1e-4
+
+
 def test_transform_of_spikes_is_closed_form():
     nx, nt, dt = 70, 90, 0.002
     p = np.zeros((nx, nt), np.float32)

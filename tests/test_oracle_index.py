@@ -1,4 +1,4 @@
-"""Pin of the table look-up (Algorithm 1 "look-up table"; Sec. III: filter
+"""Pin of the table look-up (the look-up step of Algorithm 1; Sec. III: filter
 chosen by the wavenumber omega/v): the oracle's IEEE-double index must be the
 exact-rational nearest entry wherever the exact position is not within 1e-6 of
 a tie, and must follow the stated clamps."""
