@@ -16,17 +16,31 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// B in runs of kDftRun consecutive n per thread: sincos in FP64 at the run's
+// first n and for one step of omega dt, then the run by FP64 rotation (error
+// ~1e-16 per step, far below the FP32 rounding of the entries).  Consecutive
+// threads take consecutive frequencies, so each row of B is written coalesced.
+constexpr int kDftRun = 16;
+
 __global__ void k_dft_matrix(const double* __restrict__ omega, int nw, int nt, double dt,
                              float* __restrict__ B)
 {
-    const size_t total = (size_t)nt * nw;
+    const int nrun = (nt + kDftRun - 1) / kDftRun;
+    const size_t total = (size_t)nrun * nw;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int n = (int)(e / nw), r = (int)(e % nw);
-        double s, c;
-        sincos(omega[r] * ((double)n * dt), &s, &c);
-        B[(size_t)n * 2 * nw + 2 * r] = (float)c;
-        B[(size_t)n * 2 * nw + 2 * r + 1] = (float)-s;
+        const int r = (int)(e % nw), n0 = (int)(e / nw) * kDftRun;
+        double s, c, sd, cd;
+        sincos(omega[r] * ((double)n0 * dt), &s, &c);
+        sincos(omega[r] * dt, &sd, &cd);
+        const int n1 = n0 + kDftRun < nt ? n0 + kDftRun : nt;
+        for (int n = n0; n < n1; ++n) {
+            B[(size_t)n * 2 * nw + 2 * r] = (float)c;
+            B[(size_t)n * 2 * nw + 2 * r + 1] = (float)-s;
+            const double c2 = c * cd - s * sd;
+            s = s * cd + c * sd;
+            c = c2;
+        }
     }
 }
 
@@ -208,7 +222,7 @@ __global__ void __launch_bounds__(256) k_gemm_lds(const float* __restrict__ A,
 int launch_transform(const float* section, int nx, int nt, double dt, const double* omega,
                      int nw, float2* out, float* B, hipStream_t s)
 {
-    size_t total = (size_t)nt * nw;
+    size_t total = (size_t)((nt + kDftRun - 1) / kDftRun) * nw;
     size_t blocks = (total + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_dft_matrix, dim3((unsigned)blocks), dim3(256), 0, s, omega, nw, nt, dt, B);
