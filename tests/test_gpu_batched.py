@@ -119,3 +119,29 @@ def test_batch_of_one_section_splits_blocks_like_the_planner(nx, nz, nw, reducer
     torch.cuda.synchronize()
     assert torch.isfinite(b[0]["image"]).all()
     assert torch.equal(b[0]["image"], ref)
+
+
+def test_config3_full_batch_matches_plain_and_oracle():
+    """The benchmarked batch at full size (64 sections, nx 256-2048, nz 200-800,
+    nw 100-300) in the launch configuration the benchmark's autotuner picks
+    most often: every image bit-identical to its mig_migrate, and the three
+    smallest sections against the FP64 oracle."""
+    secs = synth.config3()
+    desc = secs[0].desc
+    tab = mig.design_table(desc, dev())
+    ot = oracle.design_table(desc)[0]
+    batch = [dict(upload(s)) for s in secs]
+    print("config3: %d sections, %.2e tap-MACs" % (
+        len(secs), sum(s.nx * s.nw * (s.nz - 1) * desc.ntaps for s in secs)), flush=True)
+    mig.migrate_batched(batch, tab["tab32"], desc, tune={"omegas_per_group": 2, "reducers": 64})
+    torch.cuda.synchronize()
+    for b in batch:
+        ref = mig.migrate(b["data"], b["vel"], b["omega"], tab["tab32"], desc)
+        assert torch.equal(b["image"], ref)
+    small = sorted(range(len(secs)), key=lambda i: secs[i].nx * secs[i].nw * secs[i].nz)[:3]
+    for i in small:
+        s = secs[i]
+        ref = oracle.migrate(desc, ot, s.omega, s.vel, data64(s))
+        err = rel_l2(batch[i]["image"].cpu().numpy(), ref)
+        print("  section %d nx=%d nz=%d nw=%d: rel L2 %.2e" % (i, s.nx, s.nz, s.nw, err), flush=True)
+        assert err <= 1e-4
