@@ -150,3 +150,18 @@ def test_checkpointed_migration_is_identical_and_resumable(small):
                                 sec.desc, 16)
     assert torch.equal(nxt, cps[32])
     assert torch.equal(rows, ref[17:33])
+
+
+def test_demigrate_config2_full_matches_oracle():
+    """Demigration at the benchmarked size (1024 x 512, 200 frequencies, 35
+    taps, the layered model with its body) against the FP64 oracle adjoint."""
+    sec = synth.config2(with_data=False)
+    tab = mig.design_table(sec.desc, dev())
+    refl = sec.extra["refl"]
+    got = mig.demigrate(torch.from_numpy(refl).to(dev()), torch.from_numpy(sec.vel).to(dev()),
+                        torch.from_numpy(sec.omega).to(dev()), tab["tab32"], sec.desc)
+    ot = oracle.design_table(sec.desc)[0]
+    ref = oracle.demigrate(sec.desc, ot, sec.omega, sec.vel, refl)
+    err = rel_l2(got.cpu().numpy(), ref)
+    print("config2 demigrate rel L2 vs FP64 oracle %.3e" % err, flush=True)
+    assert err <= 1e-4
