@@ -181,8 +181,8 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
             a.ntasks = 0;
             a.nred = 0;
         }
+        // the slowness launch also zeroes the block counters
         int rc = launch_slowness(a, cs, ldp, flag_distance(kind), s);
-        if (rc == MIG_OK && rows) rc = launch_zero(cnt, (cs + kPublish - 1) / kPublish, s);
         if (rc == MIG_OK) {
             if (kind == 0) rc = launch_general(a, nx, s);
             else rc = launch_extrap(a, kind, G * threads_per_omega(kind, nx), s);
@@ -366,8 +366,8 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
             a.items = nullptr;
             a.tasks = nullptr;
         }
-        int rc = launch_zero(reinterpret_cast<int*>(base + g.cnt_off), g.ncnt, s);
-        if (rc == MIG_OK) rc = launch_slowness(a, g.max_rows, g.max_ldp, flag_distance(g.kind), s);
+        // the slowness launch also zeroes every section's block counters
+        int rc = launch_slowness(a, g.max_rows, g.max_ldp, flag_distance(g.kind), s);
         if (rc == MIG_OK) {
             if (g.kind == 0) rc = launch_general(a, g.max_nx, s);
             else rc = launch_extrap(a, g.kind, g.threads, s);

@@ -172,7 +172,6 @@ inline int flag_distance(int kind) { return kind == 1 ? 2 : (kind == 2 ? 1 : 0);
 // `kind` and `threads` (workgroup size) are the same for all items.
 int launch_extrap(const BatchArgs& a, int kind, int threads, hipStream_t s);
 int launch_general(const BatchArgs& a, int max_nx, hipStream_t s);
-int launch_zero(int* p, int n, hipStream_t s);
 // Taps per LDS pass of the demigration kernel for an LDS budget (0 = too big).
 int adjoint_chunk(int nx, int M, size_t lds_limit);
 int launch_demigrate(const AdjArgs& a, hipStream_t s);

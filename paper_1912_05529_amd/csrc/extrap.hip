@@ -159,10 +159,16 @@ __device__ __forceinline__ void group_shape(const SecDev& S, int kind, int& G, i
 }
 
 // slow[k][x] = slowness_of(vel[k][min(x, nx-1)]) for x < ldp, every section,
-// with the sign bit set where it differs (bitwise) from row k - dist.
+// with the sign bit set where it differs (bitwise) from row k - dist; also
+// zeroes each section's block counters (one launch fewer before the depth
+// stepping).
 __global__ void k_slowness(BatchArgs a, int dist)
 {
     const SecDev S = sec_of(a, blockIdx.y);
+    // the section's published-block counters start the coming launch at zero
+    if (S.cnt && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < (S.nsteps + kPublish - 1) / kPublish; i += blockDim.x)
+            S.cnt[i] = 0;
     double* slow = const_cast<double*>(S.slow);
     const size_t total = (size_t)S.nsteps * S.ldp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -554,10 +560,6 @@ __global__ void k_index(const float* __restrict__ vel, const double* __restrict_
     }
 }
 
-__global__ void k_zero(int* p, int n)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
 
 // Image rows of depth steps [s0, s1) from their partial rows, once the
 // depth-stepping launch is over: one thread per point, the frequencies added in
@@ -671,15 +673,6 @@ int launch_general(const BatchArgs& a, int max_nx, hipStream_t s)
             return MIG_E_DEVICE;
     }
     hipLaunchKernelGGL(k_extrap_general, dim3(a.nitems + a.nred), dim3(256), lds, s, a);
-    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
-}
-
-int launch_zero(int* p, int n, hipStream_t s)
-{
-    int blocks = (n + 255) / 256;
-    if (blocks > 64) blocks = 64;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
