@@ -220,7 +220,7 @@ def headline(torch, mig, synth, dev, args):
         "roofline": {
             "bound": "alu",
             "kernel": "depth-stepping launch: register-tap kernel, all %d depth steps, fused "
-                      "image rows (mig_extrapolate with rows: its two small pre-kernels, "
+                      "image rows (mig_extrapolate with rows: its small slowness pre-kernel, "
                       "the depth-stepping kernel with reducer workgroups, and the row "
                       "kernel of the last published block)" % (nz - 1),
             "achieved": round(achieved, 3),
