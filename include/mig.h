@@ -287,6 +287,7 @@ MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec,
 
 /* Diagnostic query: which extrapolation kernel a call with these sizes takes.
  * 1 = register-tap kernel, two outputs per thread (N <= 35, nx <= 1024);
+ * 3 = register-tap kernel, three outputs per thread (N <= 35, nx <= 1536);
  * 2 = register-tap kernel, four outputs per thread (N <= 35, nx <= 2048);
  * 0 = general kernel (taps read from the table every step); -1 = bad
  * arguments.  All kernels compute the same sums; results agree to FP32

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <vector>
 
 #include "common.hpp"
@@ -197,7 +199,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
 bool sizes_ok(int nx, int nw) { return nx >= 1 && nx <= MIG_MAX_NX && nw >= 1 && nw <= MIG_MAX_NW; }
 
 // ---------------------------------------------------------------------------
-// Batched form: many independent sections in at most three launches (one per
+// Batched form: many independent sections in at most four launches (one per
 // kernel variant).  The layout of the workspace is computed by one planner,
 // used both by the size query (base == nullptr) and by the run.
 // ---------------------------------------------------------------------------
@@ -211,7 +213,7 @@ struct BatchPlan {
         size_t desc_off = 0, desc_bytes = 0;  // SecDev + ItemDev + TaskDev arrays
         size_t cnt_off = 0;
         int ncnt = 0;
-    } group[3];
+    } group[4];
     size_t trash_off = 0;
 };
 
@@ -232,6 +234,18 @@ bool sections_ok(const mig_section* secs, int nsec)
             return false;
     }
     return true;
+}
+
+// Relative time of one depth step of a workgroup item in kernel `kind`: the
+// busiest SIMD runs ceil(waves / 4) waves, each with q outputs per thread
+// (the general kernel: 4 waves, ceil(nx / 256) outputs per thread).  Only
+// used to order reducer tasks.
+double step_cost(int kind, const SecDev& S)
+{
+    if (kind == 0) return (double)((S.nx + 255) / 256);
+    const int q = kind == 1 ? 2 : (kind == 2 ? 4 : 3);
+    const int waves = S.G * threads_per_omega(kind, S.nx) / 64;
+    return (double)((waves + 3) / 4 * q);
 }
 
 void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, const Tuning& tn,
@@ -274,7 +288,7 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
         g.max_ldp = S.ldp > g.max_ldp ? S.ldp : g.max_ldp;
         g.secs.push_back(S);
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         BatchPlan::Group& g = P.group[k];
         if (g.secs.empty()) continue;
         g.cnt_off = bump(off, (size_t)g.ncnt * sizeof(int));
@@ -289,22 +303,47 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
         });
         for (int si : order)
             for (int r0 = 0; r0 < g.secs[si].nw; r0 += g.secs[si].G) g.items.push_back(ItemDev{si, r0});
-        // Reducer tasks block-major across sections (production order).
         g.nred = reducer_count((int)g.items.size(), tn.nred);
         g.parts = parts_of(g.secs[0].nx);  // read by a batch of one section only
+        // Reducer tasks in the order their blocks are expected to be published
+        // (reducers take tasks round-robin and wait for each in turn).  Items
+        // start in launch order on the CUs the reducers leave free; block c of
+        // a section is published when its last-starting item has done
+        // (c + 1) * kPublish steps.
+        const int slots = device_cus() - g.nred > 1 ? device_cus() - g.nred : 1;
+        std::vector<double> last_start(g.secs.size(), 0.0);
+        std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+        for (int i = 0; i < slots; ++i) free_at.push(0.0);
+        for (const ItemDev& it : g.items) {
+            const double t0 = free_at.top();
+            free_at.pop();
+            free_at.push(t0 + g.secs[it.sec].nsteps * step_cost(k, g.secs[it.sec]));
+            last_start[it.sec] = t0 > last_start[it.sec] ? t0 : last_start[it.sec];
+        }
+        struct Blk {
+            double t;
+            int sec, c;
+        };
+        std::vector<Blk> blks;
         for (int c = 0; c < blocks_of(g.max_rows); ++c)
             for (int si : order) {
-                if (c >= blocks_of(g.secs[si].nsteps)) continue;
-                const int nx = g.secs[si].nx;
-                const int parts = parts_of(nx);
-                const int span = ((nx + parts - 1) / parts + 1) & ~1;
-                // exactly `parts` tasks per block (trailing ones may be empty), as
-                // task_of derives them for a batch of one section
-                for (int p = 0; p < parts; ++p) {
-                    const int x0 = p * span < nx ? p * span : nx;
-                    g.tasks.push_back(TaskDev{si, c, x0, x0 + span < nx ? x0 + span : nx});
-                }
+                const SecDev& S = g.secs[si];
+                if (c >= blocks_of(S.nsteps)) continue;
+                const int done = (c + 1) * kPublish < S.nsteps ? (c + 1) * kPublish : S.nsteps;
+                blks.push_back(Blk{last_start[si] + done * step_cost(k, S), si, c});
             }
+        std::stable_sort(blks.begin(), blks.end(), [](const Blk& x, const Blk& y) { return x.t < y.t; });
+        for (const Blk& b : blks) {
+            const int nx = g.secs[b.sec].nx;
+            const int parts = parts_of(nx);
+            const int span = ((nx + parts - 1) / parts + 1) & ~1;
+            // exactly `parts` tasks per block (trailing ones may be empty), as
+            // task_of derives them for a batch of one section
+            for (int p = 0; p < parts; ++p) {
+                const int x0 = p * span < nx ? p * span : nx;
+                g.tasks.push_back(TaskDev{b.sec, b.c, x0, x0 + span < nx ? x0 + span : nx});
+            }
+        }
         g.desc_bytes = g.secs.size() * sizeof(SecDev) + g.items.size() * sizeof(ItemDev) +
                        g.tasks.size() * sizeof(TaskDev);
         g.desc_off = bump(off, g.desc_bytes);
@@ -326,8 +365,8 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
     }
     const int M = (d->ntaps - 1) / 2;
     // wide sections first: their items are the longest
-    const int kinds[3] = {2, 1, 0};
-    for (int kk = 0; kk < 3; ++kk) {
+    const int kinds[4] = {2, 3, 1, 0};
+    for (int kk = 0; kk < 4; ++kk) {
         BatchPlan::Group& g = P.group[kinds[kk]];
         if (g.secs.empty()) continue;
         std::vector<char> host(g.desc_bytes);

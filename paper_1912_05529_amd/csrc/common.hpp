@@ -149,6 +149,7 @@ inline int row_stride(int nx) { return (nx + 255) / 256 * 256; }
 
 // Kernel variants (tests and the benchmark can query which one runs):
 // 1 = register taps, two outputs per thread, two tap sets (nx <= 1024);
+// 3 = register taps, three outputs per thread, one tap set (nx <= 1536);
 // 2 = register taps, four outputs per thread, one tap set (nx <= 2048);
 // 0 = general kernel, taps read from the table every step.
 int extrap_kernel_kind(int nx, int M);
@@ -167,7 +168,7 @@ int launch_index(const float* vel, const double* omega, int nx, int nw,
 // change flag taken against the row `dist` steps earlier (0 = no flags).
 int launch_slowness(const BatchArgs& a, int max_rows, int max_ldp, int dist, hipStream_t s);
 // Row distance of the change flag a kernel variant reads.
-inline int flag_distance(int kind) { return kind == 1 ? 2 : (kind == 2 ? 1 : 0); }
+inline int flag_distance(int kind) { return kind == 1 ? 2 : (kind == 0 ? 0 : 1); }
 // Depth stepping for every workgroup item (+ reducers when sections want rows).
 // `kind` and `threads` (workgroup size) are the same for all items.
 int launch_extrap(const BatchArgs& a, int kind, int threads, hipStream_t s);

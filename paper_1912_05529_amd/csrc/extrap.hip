@@ -110,25 +110,32 @@ __device__ __forceinline__ void fir2(const float2* __restrict__ win, const float
     o1 = a1;
 }
 
-// Four outputs x0..x0+3 from the window w[i] = P[x0 - M + i], i = 0..2M+3.
-template <int M>
-__device__ __forceinline__ void fir4(const float2* __restrict__ win, const float2 (&h)[4][M + 1],
-                                     float2 (&o)[4])
+// Q adjacent outputs x0..x0+Q-1 from the window w[i] = P[x0 - M + i],
+// i = 0..2M+Q-1.  Even Q: x0 is even, so the window is read with 16-byte LDS
+// loads; odd Q (x0 of either parity): 8-byte loads.
+template <int M, int Q>
+__device__ __forceinline__ void firq(const float2* __restrict__ win, const float2 (&h)[Q][M + 1],
+                                     float2 (&o)[Q])
 {
-    float2 w[2 * M + 4];
-    const float4* w4 = reinterpret_cast<const float4*>(win);
+    float2 w[2 * M + Q];
+    if constexpr (Q % 2 == 0) {
+        const float4* w4 = reinterpret_cast<const float4*>(win);
 #pragma unroll
-    for (int i = 0; i < M + 2; ++i) {
-        float4 q = w4[i];
-        w[2 * i] = make_float2(q.x, q.y);
-        w[2 * i + 1] = make_float2(q.z, q.w);
+        for (int i = 0; i < M + Q / 2; ++i) {
+            float4 q = w4[i];
+            w[2 * i] = make_float2(q.x, q.y);
+            w[2 * i + 1] = make_float2(q.z, q.w);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2 * M + Q; ++i) w[i] = win[i];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = cmulf(h[q][0], w[M + q]);
+    for (int q = 0; q < Q; ++q) o[q] = cmulf(h[q][0], w[M + q]);
 #pragma unroll
     for (int n = 1; n <= M; ++n) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o[q] = cfmaf(h[q][n], cadd(w[M + q - n], w[M + q + n]), o[q]);
+        for (int q = 0; q < Q; ++q) o[q] = cfmaf(h[q][n], cadd(w[M + q - n], w[M + q + n]), o[q]);
     }
 }
 
@@ -154,7 +161,8 @@ __device__ __forceinline__ TaskDev task_of(const BatchArgs& a, int i)
 // Per-workgroup constants: frequencies per workgroup and sub-group size.
 __device__ __forceinline__ void group_shape(const SecDev& S, int kind, int& G, int& tsub)
 {
-    tsub = kind == 1 ? ((S.nx + 1) / 2 + 63) / 64 * 64 : ((S.nx + 3) / 4 + 63) / 64 * 64;
+    const int q = kind == 1 ? 2 : (kind == 2 ? 4 : 3);  // outputs per thread
+    tsub = ((S.nx + q - 1) / q + 63) / 64 * 64;
     G = S.G;
 }
 
@@ -205,6 +213,8 @@ __device__ __forceinline__ void publish_block(const SecDev& S, int c)
 // task: an acquire invalidates the L2 of the reducer's XCD, which the
 // frequency workgroups there pay for in table refills, so tasks are whole
 // published blocks (split along x only when there are few blocks).
+constexpr int kRedDepth = 32;
+
 __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
 {
     for (int i = q; i < a.ntasks; i += a.nred) {
@@ -240,23 +250,24 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
             const int x0 = T.x0 + 2 * (it % npair);
             const float* p = S.part + (size_t)st * S.nw * S.ldp;
             __attribute__((address_space(1))) double* row = as_global(S.rows + (size_t)st * S.nx);
+            // kRedDepth loads in flight per thread (the reads are latency-bound);
+            // rows past nw are clamped loads that are not added, so the sum
+            // runs over r in increasing order like k_rows
             double a0 = 0.0, a1 = 0.0;
-            int r = 0;
-            for (; r + 8 <= S.nw; r += 8) {
-                float2 v[8];
+            for (int r = 0; r < S.nw; r += kRedDepth) {
+                float2 v[kRedDepth];
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    v[j] = load_global(reinterpret_cast<const float2*>(p + (size_t)(r + j) * S.ldp + x0));
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    a0 += (double)v[j].x;
-                    a1 += (double)v[j].y;
+                for (int j = 0; j < kRedDepth; ++j) {
+                    const int rr = r + j < S.nw ? r + j : S.nw - 1;
+                    v[j] = load_global(reinterpret_cast<const float2*>(p + (size_t)rr * S.ldp + x0));
                 }
-            }
-            for (; r < S.nw; ++r) {
-                float2 v = load_global(reinterpret_cast<const float2*>(p + (size_t)r * S.ldp + x0));
-                a0 += (double)v.x;
-                a1 += (double)v.y;
+                __builtin_amdgcn_sched_barrier(0);  // every load issued before the first add
+#pragma unroll
+                for (int j = 0; j < kRedDepth; ++j)
+                    if (r + j < S.nw) {
+                        a0 += (double)v[j].x;
+                        a1 += (double)v[j].y;
+                    }
             }
             const double nan = __builtin_nan("");
             row[x0] = ok ? a0 : nan;
@@ -326,11 +337,11 @@ template <int M, bool ROWS>
 __global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
-    if (ROWS && (int)blockIdx.x >= a.nitems) {
-        reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
+    if (ROWS && (int)blockIdx.x < a.nred) {
+        reduce_role(a, blockIdx.x, reinterpret_cast<int*>(smem4));
         return;
     }
-    const ItemDev it = item_of(a, blockIdx.x);
+    const ItemDev it = item_of(a, blockIdx.x - (ROWS ? a.nred : 0));
     const SecDev S = sec_of(a, it.sec);
     int G, tsub;
     group_shape(S, 1, G, tsub);
@@ -388,78 +399,113 @@ __global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
     }
 }
 
-// Register-tap kernel for wider sections (nx <= 4 * 512): four outputs per
-// thread and one tap set (two do not fit in 256 VGPRs), refilled at the end of
-// a step for outputs whose slowness changes at the next step.  A workgroup
-// touches only the table rows of its own frequency, so refills mostly hit in
-// L1 and the barrier covers part of their latency.  One frequency per
-// workgroup.
-template <int M, bool ROWS>
+// Write-through store of one partial-row value (see store_partial2).
+__device__ __forceinline__ void store_partial1(float* p, float a)
+{
+    __hip_atomic_store(as_global(p), a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Partial row of Q outputs.  Q = 4: x0 is a multiple of 4 and 4 * tsub is
+// the row stride, so every lane stores (lanes past nx into the padding).
+// Q = 3: 3 * tsub can pass the row stride, so only outputs inside the section
+// are stored.
+template <int Q>
+__device__ __forceinline__ void store_partial_q(float* pr, const float2 (&o)[Q], const bool (&ok)[Q])
+{
+    if constexpr (Q == 4) {
+        store_partial2(pr, o[0].x, o[1].x);
+        store_partial2(pr + 2, o[2].x, o[3].x);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (ok[q]) store_partial1(pr + q, o[q].x);
+    }
+}
+
+// Register-tap kernel for wider sections (nx <= Q * 512): Q = 3 or 4 outputs
+// per thread and one tap set (two do not fit in 256 VGPRs), refilled at the
+// end of a step for outputs whose slowness changes at the next step.  A
+// workgroup touches only the table rows of its own frequency, so refills
+// mostly hit in L1 and the barrier covers part of their latency.  One
+// frequency per workgroup.  Q = 3 serves 1024 < nx <= 1536: there Q = 4 would
+// leave 5 or 6 waves for 4 SIMDs (the SIMD with two waves sets the pace),
+// while Q = 3 gives 6 to 8 waves and three quarters of the work per wave.
+template <int M, int Q, bool ROWS>
 __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
-    if (ROWS && (int)blockIdx.x >= a.nitems) {
-        reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
+    if (ROWS && (int)blockIdx.x < a.nred) {
+        reduce_role(a, blockIdx.x, reinterpret_cast<int*>(smem4));
         return;
     }
-    const ItemDev it = item_of(a, blockIdx.x);
+    const ItemDev it = item_of(a, blockIdx.x - (ROWS ? a.nred : 0));
     const SecDev S = sec_of(a, it.sec);
     int G, tsub;
-    group_shape(S, 2, G, tsub);
+    group_shape(S, Q == 4 ? 2 : 3, G, tsub);
     if ((int)threadIdx.x >= tsub) {
         idle_barriers(2 + S.nsteps + (ROWS ? 1 : 0));
         return;
     }
     float2* sm = reinterpret_cast<float2*>(smem4);
     const int t = threadIdx.x;
-    const int LB = 4 * tsub + 2 * M + 4;
-    const int x0 = 4 * t;
+    const int LB = Q * tsub + 2 * M + 4;
+    const int x0 = Q * t;
     const bool live = it.r0 < S.nw;
     const int r = live ? it.r0 : S.nw - 1;
-    bool ok[4];
+    bool ok[Q];
+    int xs[Q];  // slowness columns, clamped into the section
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ok[q] = live && x0 + q < S.nx;
+    for (int q = 0; q < Q; ++q) {
+        ok[q] = live && x0 + q < S.nx;
+        xs[q] = x0 + q < S.nx ? x0 + q : S.nx - 1;
+    }
     const double ar = S.omega[r] / a.dk;
 
     for (int i = t; i < 2 * LB; i += tsub) sm[i] = make_float2(0.0f, 0.0f);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < Q; ++q)
         if (ok[q]) sm[M + x0 + q] = S.win[(size_t)(x0 + q) * S.nw + r];
 
-    float2 h[4][M + 1];
-    {
-        const double2* s0 = reinterpret_cast<const double2*>(S.slow + x0);
-        double c[4] = {s0[0].x, s0[0].y, s0[1].x, s0[1].y};
+    float2 h[Q][M + 1];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, slowness_value(c[q])) * (M + 1));
-    }
+    for (int q = 0; q < Q; ++q)
+        load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk, slowness_value(S.slow[xs[q]])) * (M + 1));
     __syncthreads();
 
-    float2 o[4] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f),
-                   make_float2(0.0f, 0.0f)};
+    float2 o[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) o[q] = make_float2(0.0f, 0.0f);
     for (int k = 0; k < S.nsteps; ++k) {
         wait_vmem_all();
         if (ROWS && k >= 1) {
             float* pr = live ? S.part + ((size_t)(k - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
-            store_partial2(pr, o[0].x, o[1].x);
-            store_partial2(pr + 2, o[2].x, o[3].x);
+            store_partial_q<Q>(pr, o, ok);
         }
         // slowness of step k+1 (flagged where it differs from step k), used
         // after the FIR to refill taps
         const int kp = k + 1 < S.nsteps ? k + 1 : S.nsteps - 1;
-        const double2* sp = reinterpret_cast<const double2*>(S.slow + (size_t)kp * S.ldp + x0);
-        const double2 p01 = load_global(sp), p23 = load_global(sp + 1);
-        fir4<M>(sm + (k & 1) * LB + x0, h, o);
+        const double* sp = S.slow + (size_t)kp * S.ldp;
+        double sn[Q];
+        if constexpr (Q == 4) {
+            const double2 p01 = load_global(reinterpret_cast<const double2*>(sp + x0));
+            const double2 p23 = load_global(reinterpret_cast<const double2*>(sp + x0 + 2));
+            sn[0] = p01.x;
+            sn[1] = p01.y;
+            sn[2] = p23.x;
+            sn[3] = p23.y;
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) sn[q] = *as_global(sp + xs[q]);
+        }
+        firq<M, Q>(sm + (k & 1) * LB + x0, h, o);
         float2* dst = sm + ((k + 1) & 1) * LB + M + x0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < Q; ++q)
             if (ok[q]) dst[q] = o[q];
         if (k + 1 < S.nsteps) {
-            const double sn[4] = {p01.x, p01.y, p23.x, p23.y};
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < Q; ++q)
                 if (slowness_changed(sn[q]))
                     load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
                                                                          slowness_value(sn[q])) * (M + 1));
@@ -470,15 +516,14 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
     }
     if (ROWS) {
         float* pr = live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
-        store_partial2(pr, o[0].x, o[1].x);
-        store_partial2(pr + 2, o[2].x, o[3].x);
+        store_partial_q<Q>(pr, o, ok);
         wait_vmem_all();
         __syncthreads();
         publish_block(S, (S.nsteps - 1) / kPublish);
     }
     if (S.wout) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < Q; ++q)
             if (ok[q]) S.wout[(size_t)(x0 + q) * S.nw + r] = o[q];
     }
 }
@@ -489,11 +534,11 @@ __global__ void __launch_bounds__(256) k_extrap_general(BatchArgs a)
 {
     extern __shared__ float4 smem4[];
     const bool rows_on = a.rows != 0;
-    if (rows_on && (int)blockIdx.x >= a.nitems) {
-        reduce_role(a, blockIdx.x - a.nitems, reinterpret_cast<int*>(smem4));
+    if (rows_on && (int)blockIdx.x < a.nred) {
+        reduce_role(a, blockIdx.x, reinterpret_cast<int*>(smem4));
         return;
     }
-    const ItemDev it = item_of(a, blockIdx.x);
+    const ItemDev it = item_of(a, blockIdx.x - (rows_on ? a.nred : 0));
     const SecDev S = sec_of(a, it.sec);
     float2* sm = reinterpret_cast<float2*>(smem4);
     const int M = a.M, nx = S.nx;
@@ -598,15 +643,27 @@ int launch_fast(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
-template <int M>
+template <int M, int Q>
 int launch_wide(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
 {
     if (a.rows)
-        hipLaunchKernelGGL((k_extrap_wide<M, true>), dim3(a.nitems + a.nred), dim3(threads), lds,
-                           s, a);
+        hipLaunchKernelGGL((k_extrap_wide<M, Q, true>), dim3(a.nitems + a.nred), dim3(threads),
+                           lds, s, a);
     else
-        hipLaunchKernelGGL((k_extrap_wide<M, false>), dim3(a.nitems), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_extrap_wide<M, Q, false>), dim3(a.nitems), dim3(threads), lds, s, a);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+template <int M>
+int launch_wide4(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
+{
+    return launch_wide<M, 4>(a, threads, lds, s);
+}
+
+template <int M>
+int launch_wide3(const BatchArgs& a, int threads, size_t lds, hipStream_t s)
+{
+    return launch_wide<M, 3>(a, threads, lds, s);
 }
 
 typedef int (*launch_fn)(const BatchArgs&, int, size_t, hipStream_t);
@@ -617,9 +674,11 @@ typedef int (*launch_fn)(const BatchArgs&, int, size_t, hipStream_t);
     {&f<0>, &f<1>, &f<2>, &f<3>, &f<4>, &f<5>, &f<6>, &f<7>, &f<8>, &f<9>, &f<10>,     \
      &f<11>, &f<12>, &f<13>, &f<14>, &f<15>, &f<16>, &f<17>}
 const launch_fn kFast[] = MIG_INST(launch_fast);
-const launch_fn kWide[] = MIG_INST(launch_wide);
+const launch_fn kWide[] = MIG_INST(launch_wide4);
+const launch_fn kMid[] = MIG_INST(launch_wide3);
 constexpr int kRegMaxM = 17;
 constexpr int kFastMaxNx = 2 * 512;
+constexpr int kMidMaxNx = 3 * 512;
 constexpr int kWideMaxNx = 4 * 512;
 
 }  // namespace
@@ -628,6 +687,7 @@ int extrap_kernel_kind(int nx, int M)
 {
     if (M > kRegMaxM) return 0;
     if (nx <= kFastMaxNx) return 1;
+    if (nx <= kMidMaxNx) return 3;
     if (nx <= kWideMaxNx) return 2;
     return 0;
 }
@@ -636,6 +696,7 @@ int threads_per_omega(int kind, int nx)
 {
     if (kind == 1) return ((nx + 1) / 2 + 63) / 64 * 64;
     if (kind == 2) return ((nx + 3) / 4 + 63) / 64 * 64;
+    if (kind == 3) return ((nx + 2) / 3 + 63) / 64 * 64;
     return 256;
 }
 
@@ -656,9 +717,10 @@ int launch_extrap(const BatchArgs& a, int kind, int threads, hipStream_t s)
         size_t lds = (size_t)2 * (2 * threads + (threads / tsub_min) * (2 * a.M + 2)) * sizeof(float2);
         return kFast[a.M](a, threads, lds, s);
     }
-    if (kind == 2) {
-        size_t lds = (size_t)2 * (4 * threads + 2 * a.M + 4) * sizeof(float2);
-        return kWide[a.M](a, threads, lds, s);
+    if (kind == 2 || kind == 3) {
+        const int Q = kind == 2 ? 4 : 3;
+        size_t lds = (size_t)2 * (Q * threads + 2 * a.M + 4) * sizeof(float2);
+        return (kind == 2 ? kWide : kMid)[a.M](a, threads, lds, s);
     }
     return MIG_E_ARG;
 }

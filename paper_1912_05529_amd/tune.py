@@ -19,7 +19,7 @@ from . import mig
 _cache: dict = {}
 
 OMEGAS_PER_GROUP = (1, 2, 4, 8)
-REDUCERS = (0, 16, 32, 64)
+REDUCERS = (0, 16, 24, 32, 48, 64)
 
 
 def signature(batch, desc) -> tuple:

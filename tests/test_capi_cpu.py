@@ -86,7 +86,9 @@ def test_workspace_sizes_and_kernel_kinds(L):
     plane_1000 = (1000 * 7 * 8 + 255) // 256 * 256 + 16384 + 1024 * 4
     assert mig.workspace_size(1000, 3, 7, d) == plane_1000 + 3 * (1024 * 8 + 7 * 1024 * 4)
     assert mig.kernel_kind(1024, 35) == 1
-    assert mig.kernel_kind(1025, 35) == 2
+    assert mig.kernel_kind(1025, 35) == 3
+    assert mig.kernel_kind(1536, 35) == 3
+    assert mig.kernel_kind(1537, 35) == 2
     assert mig.kernel_kind(2048, 25) == 2
     assert mig.kernel_kind(2049, 25) == 0
     assert mig.kernel_kind(512, 37) == 0

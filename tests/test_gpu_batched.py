@@ -28,10 +28,11 @@ def _batch(shapes, seed=50, ntaps=35):
 
 
 SHAPES = [
-    # nx, nz, nw, layered: kinds 1, 1 (G>1), 2, 0 (nx > 2048), nz = 1, nz = 2
+    # nx, nz, nw, layered: kinds 1, 1 (G>1), 3, 2, 0 (nx > 2048), nz = 1, nz = 2
     (300, 40, 13, True),
     (100, 25, 9, False),
     (1500, 20, 5, True),
+    (1800, 15, 4, False),
     (2100, 9, 3, False),
     (64, 1, 4, True),
     (700, 2, 6, False),
@@ -105,7 +106,7 @@ def test_autotuner_picks_a_measured_candidate(mixed):
 
 @pytest.mark.parametrize("nx,nz,nw,reducers", [(1024, 40, 8, 24), (1024, 40, 8, 48),
                                                (777, 70, 5, 32), (300, 18, 3, 64),
-                                               (1500, 33, 4, 40)])
+                                               (1500, 33, 4, 40), (1900, 33, 4, 40)])
 def test_batch_of_one_section_splits_blocks_like_the_planner(nx, nz, nw, reducers):
     """A batch of one section derives its reducer tasks from the split count;
     with enough reducers each published block is split along x, and the

@@ -87,6 +87,9 @@ CASES = [
     (1024, 3, 4, 35, False),
     (1025, 3, 4, 35, True),
     (1500, 2, 5, 25, False),
+    (1280, 3, 6, 35, True),
+    (1536, 2, 4, 35, False),
+    (1537, 2, 3, 35, True),
     (2048, 2, 3, 35, True),
     (2049, 2, 3, 35, False),
     (300, 3, 4, 37, False),
@@ -192,12 +195,15 @@ def test_extrapolate_zero_steps_and_errors(tables):
 
 @pytest.mark.parametrize("nx,nw,nsteps,ntaps", [(1024, 600, 20, 35), (130, 37, 33, 35),
                                                (2000, 9, 17, 35), (1024, 300, 97, 35),
-                                               (2100, 40, 40, 35), (300, 60, 70, 41)])
+                                               (2100, 40, 40, 35), (300, 60, 70, 41),
+                                               (1280, 50, 40, 35)])
 def test_fused_reduction_rows_match_oracle(nx, nw, nsteps, ntaps, tables):
     """Image rows formed inside the depth-stepping launch (reducer workgroups)
     and, for the last published block, after it: more frequency workgroups than
     CUs, several publish blocks with a ragged last block, the
-    four-outputs-per-thread kernel and the general kernel (nx > 2048, N > 35)."""
+    three- and four-outputs-per-thread kernels (1280 points: three outputs per
+    thread reach past the row stride) and the general kernel (nx > 2048,
+    N > 35)."""
     sec = synth.random_case(3000 + nx + nw, nx, nsteps + 1, nw, ntaps=ntaps, nk=256)
     (ot, _, _, _), g = tables(sec.desc)
     print("fused rows nx=%d nw=%d nsteps=%d N=%d kind=%d" % (nx, nw, nsteps, ntaps,
