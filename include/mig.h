@@ -246,7 +246,7 @@ MIG_API int mig_demigrate(const double* image, const float* vel,
 
 /*
  * Batched form: many independent 2-D sections (different nx, nz, nw, all
- * sharing one table) migrated in at most three launches -- one per kernel
+ * sharing one table) migrated in at most four launches -- one per kernel
  * variant -- instead of one per section.  Every section is Algorithm 1 end to
  * end exactly as mig_migrate computes it (bit-identical results for the same
  * tuning), so this is a scheduling form of the same method: frequency
