@@ -62,7 +62,8 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 // Fixed workspace region for the published-block counters of one launch.
 constexpr size_t kCounterBytes = 16384;
-constexpr int kMaxBlocks = (int)(kCounterBytes / sizeof(int));
+// the last counter is the launch's publish count (reducers' stall clock)
+constexpr int kMaxBlocks = (int)(kCounterBytes / sizeof(int)) - 1;
 constexpr int kMaxChunk = kMaxBlocks * kPublish;
 constexpr int kMaxThreads = 512;
 
@@ -149,6 +150,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
     a.one.G = G;
     a.tab = tab;
     a.trash = trash;
+    a.progress = cnt + kMaxBlocks;
     a.nsec = 1;
     a.nitems = nitems;
     a.nk = d->nk;
@@ -291,7 +293,7 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
     for (int k = 0; k < 4; ++k) {
         BatchPlan::Group& g = P.group[k];
         if (g.secs.empty()) continue;
-        g.cnt_off = bump(off, (size_t)g.ncnt * sizeof(int));
+        g.cnt_off = bump(off, (size_t)(g.ncnt + 1) * sizeof(int));  // + the publish count
         for (SecDev& S : g.secs)
             S.cnt = reinterpret_cast<int*>(base ? base + g.cnt_off + (size_t)S.cnt * sizeof(int) : nullptr);
         // Items: longest first (depth steps x points), so the tail of the
@@ -386,6 +388,7 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
                                                    g.items.size() * sizeof(ItemDev));
         a.tab = tab;
         a.trash = reinterpret_cast<float*>(base + P.trash_off);
+        a.progress = reinterpret_cast<int*>(base + g.cnt_off) + g.ncnt;
         a.nsec = (int)g.secs.size();
         a.nitems = (int)g.items.size();
         a.ntasks = (int)g.tasks.size();

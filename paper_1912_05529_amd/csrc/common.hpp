@@ -55,6 +55,7 @@ struct BatchArgs {
     const TaskDev* tasks;
     const float2* tab;     // [nk][M+1] complex64 half-taps
     float* trash;          // [ldp_max] sink for partial rows of idle sub-groups
+    int* progress;         // publishes of the whole launch (reducers' stall clock)
     int nsec, nitems, ntasks, nred;
     int rows;              // frequency workgroups write and publish partial rows
     int parts;             // x-parts per block (nsec == 1)

@@ -177,6 +177,7 @@ __global__ void k_slowness(BatchArgs a, int dist)
     if (S.cnt && blockIdx.x == 0)
         for (int i = threadIdx.x; i < (S.nsteps + kPublish - 1) / kPublish; i += blockDim.x)
             S.cnt[i] = 0;
+    if (a.progress && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.progress = 0;
     double* slow = const_cast<double*>(S.slow);
     const size_t total = (size_t)S.nsteps * S.ldp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -195,16 +196,17 @@ __global__ void k_slowness(BatchArgs a, int dist)
 }
 
 // Thread 0 of a frequency workgroup, after a barrier that follows the stores of
-// the partial rows of block c: count the block.  The partial rows are stored
+// the partial rows of block c: count the block (and the launch's publishes).  The partial rows are stored
 // write-through (agent-scope atomic stores) and every wave waits for its own
 // stores to complete before that barrier (wait_vmem_all), so when the counter
 // moves the rows are already where other XCDs read them.  No release fence:
 // at agent scope it would write back the whole L2 of the XCD, which the
 // barrier after the next step would make every wave of the workgroup wait for.
-__device__ __forceinline__ void publish_block(const SecDev& S, int c)
+__device__ __forceinline__ void publish_block(const BatchArgs& a, const SecDev& S, int c)
 {
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(as_global(S.cnt + c), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(as_global(a.progress), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -222,13 +224,19 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
         const SecDev S = sec_of(a, T.sec);
         if (T.block * kPublish >= S.nsteps) continue;  // no such block (uniform)
         if (threadIdx.x == 0) {
-            int v, last = -1;
+            // the stall clock restarts whenever the block's counter or the
+            // launch's publish count moves: a section whose items start late
+            // in a long batch is waited for, a launch that stops is not
+            int v, last = -1, seen = -1;
             unsigned long long t0 = wall_clock64();
             while ((v = __hip_atomic_load(as_global(S.cnt + T.block), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT)) < S.nprod) {
+                const int g = __hip_atomic_load(as_global(a.progress), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
                 unsigned long long now = wall_clock64();
-                if (v != last) {
+                if (v != last || g != seen) {
                     last = v;
+                    seen = g;
                     t0 = now;
                 } else if (now - t0 > kStallTicks) {
                     break;
@@ -327,7 +335,7 @@ __device__ __forceinline__ void step_fast(const BatchArgs& a, const SecDev& S, f
     if (ROWS && k >= 1 && k % kPublish == 0) wait_vmem_all();
     __syncthreads();
     // the partial row of step k-1 is now stored by every thread
-    if (ROWS && k >= 1 && k % kPublish == 0) publish_block(S, (k - 1) / kPublish);
+    if (ROWS && k >= 1 && k % kPublish == 0) publish_block(a, S, (k - 1) / kPublish);
 }
 
 // Register-tap kernel, two outputs per thread.  Sub-group of tsub threads per
@@ -391,7 +399,7 @@ __global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
         store_partial2(pr, o0.x, o1.x);
         wait_vmem_all();
         __syncthreads();
-        publish_block(S, (S.nsteps - 1) / kPublish);
+        publish_block(a, S, (S.nsteps - 1) / kPublish);
     }
     if (S.wout) {
         if (L.ok0) S.wout[(size_t)L.x0 * S.nw + L.r] = o0;
@@ -512,14 +520,14 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
         }
         if (ROWS && k >= 1 && k % kPublish == 0) wait_vmem_all();
         __syncthreads();
-        if (ROWS && k >= 1 && k % kPublish == 0) publish_block(S, (k - 1) / kPublish);
+        if (ROWS && k >= 1 && k % kPublish == 0) publish_block(a, S, (k - 1) / kPublish);
     }
     if (ROWS) {
         float* pr = live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
         store_partial_q<Q>(pr, o, ok);
         wait_vmem_all();
         __syncthreads();
-        publish_block(S, (S.nsteps - 1) / kPublish);
+        publish_block(a, S, (S.nsteps - 1) / kPublish);
     }
     if (S.wout) {
 #pragma unroll
@@ -566,7 +574,7 @@ __global__ void __launch_bounds__(256) k_extrap_general(BatchArgs a)
         const bool publish = rows_on && ((k + 1) % kPublish == 0 || k + 1 == S.nsteps);
         if (publish) wait_vmem_all();
         __syncthreads();
-        if (publish) publish_block(S, k / kPublish);
+        if (publish) publish_block(a, S, k / kPublish);
     }
     if (S.wout && live) {
         const float2* src = sm + (S.nsteps & 1) * LB + M;
