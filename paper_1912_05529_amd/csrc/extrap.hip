@@ -29,14 +29,16 @@
 //     Each frequency sub-group writes Re of its new plane (float32, exact) to a
 //     partial buffer [step][omega][x], write-through; every kPublish steps the
 //     workgroup publishes its progress (its stores complete, then a counter
-//     increment).  Reducer workgroups in the same launch -- on CUs the
-//     frequency workgroups leave idle -- wait for a block of steps to be
+//     increment).  Reducer workgroups in the same launch -- the first
+//     workgroups of the grid, so they run beside the frequency workgroups from
+//     the start even when items outnumber the CUs -- take blocks in the order
+//     they are expected to be published, wait for a block of steps to be
 //     published by every workgroup of the section, acquire, and sum it over
 //     omega in increasing order in FP64, so images are run-to-run identical
-//     and the reduction overlaps the extrapolation; the last block is summed
-//     after the launch (k_rows) by the whole GPU.  Frequency workgroups never
-//     wait on anyone; reducer waits are bounded (a stall of kStallTicks writes
-//     NaN rows instead of hanging).
+//     and the reduction overlaps the extrapolation; the last block of a plain
+//     launch is summed after it (k_rows) by the whole GPU.  Frequency
+//     workgroups never wait on anyone; reducer waits are bounded (kStallTicks
+//     without any publish in the launch writes NaN rows instead of hanging).
 #include "common.hpp"
 
 namespace mig {
