@@ -61,7 +61,7 @@ class OrcDesc:
     nreweight: int = 30
     lam: float | None = None  # None -> 1e-9 * ngrid
     beta: float = 1.0
-    tau: float = 1e-4
+    tau: float = 5e-4
     margin: float = 1e-5
 
     @classmethod

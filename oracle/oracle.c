@@ -389,9 +389,9 @@ int orc_demigrate(const orc_desc* d, const double* tab, const double* omega,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Transform along t (Algorithm 1: "Fourier transform of shot gather along  */
-/* t-axis"; Sec. III), evaluated directly at the requested frequencies with */
-/* the forward sign exp(-i omega t).                                        */
+/* Transform along t (first step of Algorithm 1; Sec. III), evaluated     */
+/* directly at the requested frequencies with the forward sign             */
+/* exp(-i omega t).                                                         */
 /* ------------------------------------------------------------------------ */
 int orc_transform_t(const float* p, int32_t nx, int32_t nt, double dt,
                     const double* omega, int32_t nw, double* out)

@@ -63,7 +63,7 @@ class TableDesc:
     nreweight: int = 30
     lam: float | None = None  # None -> 1e-9 * ngrid
     beta: float = 1.0
-    tau: float = 1e-4
+    tau: float = 5e-4
     margin: float = 1e-5
 
     @property
@@ -328,9 +328,10 @@ def table2d_for(ntaps: int, nk: int, fmin: float, fmax: float, vmin_prop: float,
                 ncheck: int = 192, tau: float = 1e-2, beta: float = 0.3,
                 **kw) -> TableDesc:
     """2-D table descriptor; ngrid/ncheck are points per axis of the 2-D grids.
-    The reweighting is gentler than in 1-D (tau 1e-2, beta 0.3): with the 1-D
-    values the 2-D fit becomes ill-conditioned at large kappa (1-ulp input
-    changes move some entries by 1e-4) and its worst passband error grows."""
+    The reweighting is gentler than in 1-D (tau 1e-2, beta 0.3): with beta 1
+    and tau of order 1e-4 the 2-D fit becomes ill-conditioned at large kappa
+    (1-ulp input changes move some entries by 1e-4) and its worst passband
+    error grows."""
     return table_for(ntaps, nk, fmin, fmax, vmin_prop, vmax_prop, dx, dz, ngrid=ngrid,
                      ncheck=ncheck, tau=tau, beta=beta, **kw)
 

@@ -77,12 +77,16 @@ def test_design2d_single_coefficient_is_weighted_mean():
         assert abs(tab[j, 0] - want) <= 1e-13 * max(1.0, abs(want))
 
 
-@pytest.mark.parametrize("ntaps", [3, 5, 7])
-def test_design2d_matches_weighted_lstsq_of_expanded_filter(ntaps):
+@pytest.mark.parametrize("ntaps,nreweight", [(3, 0), (5, 0), (7, 0), (5, 2), (7, 1), (7, 3)])
+def test_design2d_matches_weighted_lstsq_of_expanded_filter(ntaps, nreweight):
+    """Weighted least squares with the basis built from the expanded filter,
+    solved by numpy's lstsq, followed by `nreweight` passes that multiply the
+    weight of every design point with |H| > 1 by 1 + beta (|H| - 1) / tau
+    and solve again."""
     M = (ntaps - 1) // 2
     NU = (M + 1) * (M + 2) // 2
     lam = 1e-6
-    desc = small_desc(ntaps, nreweight=0, lam=lam)
+    desc = small_desc(ntaps, nreweight=nreweight, lam=lam)
     tab, _, _, _ = oracle.design_table_2d(desc, apply_scale=False)
     tx, ty = grid(desc.ngrid)
     # columns: response of the expanded filter with one unique coefficient set
@@ -94,14 +98,29 @@ def test_design2d_matches_weighted_lstsq_of_expanded_filter(ntaps):
     A = np.stack(cols, axis=1)
     assert np.max(np.abs(A.imag)) < 1e-12          # the expanded filters are real-symmetric
     A = A.real
+    moved = 0.0
     for j in (0, desc.nk // 2, desc.nk - 1):
         D, w, _ = target(desc, j, tx, ty)
-        sw = np.sqrt(w.ravel())
-        Aw = np.vstack([A * sw[:, None], math.sqrt(lam) * np.eye(NU)])
-        bw = np.concatenate([D.ravel() * sw, np.zeros(NU)])
-        want = np.linalg.lstsq(Aw, bw, rcond=None)[0]
+        w = w.ravel().astype(np.float64)
+
+        def solve(wt):
+            sw = np.sqrt(wt)
+            Aw = np.vstack([A * sw[:, None], math.sqrt(lam) * np.eye(NU)])
+            bw = np.concatenate([D.ravel() * sw, np.zeros(NU)])
+            return np.linalg.lstsq(Aw, bw, rcond=None)[0]
+
+        want = solve(w)
+        first = want
+        for _ in range(nreweight):
+            excess = np.abs(A @ want) - 1.0
+            w = w * (1.0 + desc.beta * np.maximum(excess, 0.0) / desc.tau)
+            want = solve(w)
+        moved = max(moved, float(np.max(np.abs(want - first)) / np.max(np.abs(want))))
         err = np.max(np.abs(tab[j] - want)) / np.max(np.abs(want))
-        assert err <= 1e-8, (j, err)
+        assert err <= 1e-10, (j, err)
+    if nreweight:
+        # the passes change the taps far beyond the agreement asked for above
+        assert moved > 1e-6, moved
 
 
 @pytest.mark.parametrize("ntaps", [5, 11])

@@ -7,6 +7,7 @@ it: the DCT-II (textbook special case), the Bernstein bound for trigonometric
 polynomials (stability), the zero-thickness identity, and an independently
 coded phase-shift target for the reported passband error.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -99,12 +100,69 @@ def test_p3_design_quality_cfg1(cfg1, cfg1_table):
 
 
 def test_p3_design_quality_cfg2(cfg2_model, cfg2_table):
+    """Sanity bounds per band of kappa = k dx.  The worst propagating-band
+    errors sit at small kappa (<= 0.5: 0.023): there the passband holds only
+    a few grid points and the target's kink at theta = kappa, followed by
+    the evanescent decay over most of (0, pi), is what 35 even taps cannot
+    follow.  Between 1.5 and 3.25 the error stays below 0.015; above 3.25 the
+    entries are spatially aliased (k dx near pi) and reach 0.075."""
     tab, mg, pe, sc = cfg2_table
     kap = _entries(cfg2_model.desc)
     assert sc.min() >= 0.9999
-    assert pe[kap <= 3.25].max() <= 0.03
+    assert pe[kap <= 0.5].max() <= 0.03
+    assert pe[(kap > 0.5) & (kap <= 1.5)].max() <= 0.02
+    assert pe[(kap > 1.5) & (kap <= 3.25)].max() <= 0.015
     assert pe.max() <= 0.1
     assert mg.max() <= 1.0
+
+
+def _numpy_reweighted_design(desc, j, nreweight):
+    """The design of entry j written independently: weighted least squares
+    by numpy's lstsq on the sqrt(w)-scaled system (plus sqrt(lambda) I rows
+    for the diagonal term), then `nreweight` passes that multiply the weight
+    of every design point with |H| > 1 by 1 + beta (|H| - 1) / tau and solve
+    again.  No stability scale."""
+    M = (desc.ntaps - 1) // 2
+    L = desc.ngrid
+    dk = (desc.kmax - desc.kmin) / (desc.nk - 1)
+    kappa = (desc.kmin + j * dk) * desc.dx
+    theta = (np.arange(L) + 0.5) * math.pi / L
+    D = _phase_shift(kappa, theta, desc.dx, desc.dz)
+    edge = kappa * math.sin(math.radians(desc.theta_max_deg))
+    w = np.where(theta <= edge, desc.w_pass,
+                 np.where(theta <= kappa, desc.w_trans, desc.w_evan)).astype(np.float64)
+    A = np.cos(np.outer(theta, np.arange(M + 1)))
+    A[:, 1:] *= 2.0
+    lam = desc.lam if desc.lam is not None else 1e-9 * L
+
+    def solve(wt):
+        sw = np.sqrt(wt)
+        Aw = np.vstack([A * sw[:, None], math.sqrt(lam) * np.eye(M + 1)])
+        bw = np.concatenate([D * sw, np.zeros(M + 1)])
+        return np.linalg.lstsq(Aw, bw, rcond=None)[0]
+
+    h = solve(w)
+    for _ in range(nreweight):
+        excess = np.abs(A @ h) - 1.0
+        w = w * (1.0 + desc.beta * np.maximum(excess, 0.0) / desc.tau)
+        h = solve(w)
+    return h
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+@pytest.mark.parametrize("nreweight", [1, 2, 3])
+def test_reweighting_passes_match_numpy_lstsq(which, nreweight, cfg1, cfg2_model):
+    """The reweighting passes of the design (a step the paper leaves open,
+    Sec. II) against an independent numpy loop.  Each extra pass moves the
+    taps by 1e-4 to 1e-3, and halving beta by 2e-3, far above the 1e-10
+    agreement required here."""
+    base = (cfg1 if which == "cfg1" else cfg2_model).desc
+    desc = dataclasses.replace(base, nk=17, nreweight=nreweight)
+    tab, _, _, _ = oracle.design_table(desc, apply_scale=False)
+    for j in range(desc.nk):
+        want = _numpy_reweighted_design(desc, j, nreweight)
+        err = np.abs(tab[j] - want).max() / np.abs(want).max()
+        assert err <= 1e-10, (j, err)
 
 
 def test_p6_zero_thickness_is_identity():
