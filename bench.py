@@ -463,7 +463,7 @@ def volume3d(torch, mig, synth, dev, args, profile=False):
     if not args.no_cpu_baseline:
         import oracle
         k = 3
-        otab = tab["tab64"].cpu().numpy()
+        otab = oracle.design_table_2d(desc)[0]   # the oracle's own table
         t0 = time.time()
         ref = oracle.migrate3d(desc, otab, vol.omega, np.ascontiguousarray(vol.vel[:k + 1]),
                                vol.data.astype(np.complex64).astype(np.complex128))

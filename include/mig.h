@@ -99,7 +99,7 @@ typedef struct {
     int32_t nreweight;      /* >= 0 (default 30)                              */
     int32_t reserved;       /* must be 0                                      */
     double lambda;          /* >= 0 (default 1e-9 * ngrid)                    */
-    double beta, tau;       /* reweighting gain and scale (defaults 1, 1e-4)  */
+    double beta, tau;       /* reweighting gain and scale (defaults 1, 5e-4)  */
     double margin;          /* stability margin in [0, 1) (default 1e-5)     */
 } mig_table_desc;
 
@@ -145,13 +145,29 @@ MIG_API int mig_table_index(const float* vel, const double* omega,
                             int32_t nrows, int32_t* idx, void* stream);
 
 /* Bytes of workspace mig_extrapolate (with or without rows) and mig_migrate
- * need to run all `nsteps` depth steps in one launch.  A smaller workspace (at
- * least mig_workspace_min_size) makes the library split the depth loop into
- * chunks of as many steps as fit; results are bit-identical. */
+ * need to run `nsteps` depth steps in one launch (for mig_migrate, nsteps =
+ * nz - 1: the number of depth steps, not of image rows).  A smaller workspace
+ * (at least mig_workspace_min_size) makes the library split the depth loop
+ * into chunks of as many steps as fit; results are bit-identical. */
 MIG_API size_t mig_workspace_size(int32_t nx, int32_t nsteps, int32_t nw,
                                   const mig_table_desc* d);
 MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw,
                                       const mig_table_desc* d);
+
+/*
+ * Status of the most recent call of mig_extrapolate, mig_migrate or
+ * mig_migrate_batched that used the workspace `ws`.  The image rows are
+ * summed over frequencies inside the depth-stepping launch by reducer
+ * workgroups that wait for the frequency workgroups' published blocks; each
+ * wait is bounded (20 s without any publish in the launch, or the limit of
+ * mig_tuning), and a reducer that runs into the bound gives up for the
+ * whole launch: the rows it and every later reducer task would have formed
+ * are written as NaN and a status word at the head of the workspace is set.
+ * Since calls are asynchronous, that status is read here: the call
+ * synchronizes `stream` and returns MIG_OK, or MIG_E_DEVICE if a reduction
+ * was abandoned (or the read failed).  MIG_E_ARG for ws == NULL.
+ */
+MIG_API int mig_workspace_status(const void* ws, void* stream);
 
 /*
  * A2 + A3 + A4 -- advance a plane by `nsteps` depth steps with Eq. (1) in FP32
@@ -255,8 +271,12 @@ MIG_API int mig_demigrate(const double* image, const float* vel,
  *   secs   [nsec] host array of section descriptors (read during the call)
  *   tune   knobs chosen by an autotuner, or NULL for the library defaults
  *   ws     >= mig_batch_workspace_size(secs, nsec, d, tune) bytes of device
- *          memory (slowness rows, partial image rows and descriptors of every
- *          section; no chunking)
+ *          memory (status word, slowness rows, partial image rows and the
+ *          device copy of the launch descriptors; no chunking)
+ * The launch descriptors are built on the host and copied into `ws` from a
+ * buffer the call owns, so the call blocks until that copy (and the earlier
+ * work of `stream`) has completed; the launches themselves are asynchronous.
+ * It therefore cannot be captured into a HIP graph.
  */
 typedef struct {
     const mig_c64* data;   /* [nx][nw] surface plane                        */
@@ -273,9 +293,17 @@ typedef struct {
                                  512 threads); clamped to what fits          */
     int32_t reducers;         /* reducer workgroups per launch, 8..64
                                  (0 = the CUs the frequency workgroups leave
-                                 idle, at least 8)                           */
-    int32_t reserved[2];      /* must be 0                                   */
+                                 idle, at least 8); never more than a quarter
+                                 of the device's CUs                         */
+    int32_t stall_limit_us;   /* reducer stall limit in microseconds
+                                 (0 = 20 s); see mig_workspace_status        */
+    int32_t flags;            /* 0, or MIG_TUNE_FORCE_STALL                 */
 } mig_tuning;
+
+/* Test hook for the failure path: reducers wait for one publish more than
+ * the frequency workgroups make, so every wait runs into the stall limit and
+ * the launch is abandoned (every kernel still ends normally). */
+#define MIG_TUNE_FORCE_STALL 1
 
 MIG_API size_t mig_batch_workspace_size(const mig_section* secs, int32_t nsec,
                                         const mig_table_desc* d,

@@ -62,8 +62,9 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 // Fixed workspace region for the published-block counters of one launch.
 constexpr size_t kCounterBytes = 16384;
-// the last counter is the launch's publish count (reducers' stall clock)
-constexpr int kMaxBlocks = (int)(kCounterBytes / sizeof(int)) - 1;
+// the last two words are the launch's publish count (reducers' stall clock)
+// and its abandon word
+constexpr int kMaxBlocks = (int)(kCounterBytes / sizeof(int)) - 2;
 constexpr int kMaxChunk = kMaxBlocks * kPublish;
 constexpr int kMaxThreads = 512;
 
@@ -77,13 +78,17 @@ int device_cus()
 }
 
 // Reducer workgroups beside `nprod` frequency workgroups: the CUs they leave
-// idle, at least 8, at most 64 (before capping by the number of tasks).
+// idle, at least 8, at most 64 (before capping by the number of tasks), and
+// never more than a quarter of the device's CUs, so that frequency
+// workgroups always find CUs to run on while reducers wait for them.
 int reducer_count(int nprod, int want)
 {
-    int n = want > 0 ? want : device_cus() - nprod;
+    const int cus = device_cus();
+    const int cap = cus / 4 > 1 ? cus / 4 : 1;
+    int n = want > 0 ? want : cus - nprod;
     if (n < 8) n = 8;
     if (n > 64) n = 64;
-    return n;
+    return n < cap ? n : cap;
 }
 
 int blocks_of(int nsteps) { return (nsteps + kPublish - 1) / kPublish; }
@@ -107,19 +112,59 @@ int omegas_per_group(int kind, int nx, int want)
 }
 
 struct Tuning {
-    int G;      // frequencies per workgroup (0 = default)
-    int nred;   // reducer workgroups (0 = default)
+    int G = 0;              // frequencies per workgroup (0 = default)
+    int nred = 0;           // reducer workgroups (0 = default)
+    int stall_us = 0;       // reducer stall limit in microseconds (0 = default)
+    int flags = 0;          // MIG_TUNE_* bits
 };
 
+Tuning tuning_of(const mig_tuning* t)
+{
+    Tuning tn;
+    if (t) {
+        tn.G = t->omegas_per_group;
+        tn.nred = t->reducers;
+        tn.stall_us = t->stall_limit_us;
+        tn.flags = t->flags;
+    }
+    return tn;
+}
+
+bool tuning_valid(const mig_tuning* t)
+{
+    return !t || (t->omegas_per_group >= 0 && t->reducers >= 0 && t->stall_limit_us >= 0 &&
+                  (t->flags & ~MIG_TUNE_FORCE_STALL) == 0);
+}
+
+// Calls that run no depth step still leave a defined status in a workspace
+// they were given.
+int clear_status(void* ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!ws || ws_bytes < kStatusBytes) return MIG_OK;
+    return launch_clear_status(static_cast<int*>(ws), s);
+}
+
+void set_reducer_limits(BatchArgs& a, const Tuning& tn)
+{
+    a.stall_ticks = tn.stall_us > 0 ? (unsigned long long)tn.stall_us * kWallTicksPerUs : kStallTicks;
+    a.extra_wait = (tn.flags & MIG_TUNE_FORCE_STALL) ? 1 : 0;
+}
+
+// Bytes of the depth-loop workspace before the per-step regions.
+size_t extrap_head_bytes(int nx, int nw)
+{
+    return kStatusBytes + plane_bytes(nx, nw) + kCounterBytes + (size_t)row_stride(nx) * sizeof(float);
+}
+
 // Depth loop of one section, split into chunks that fit the workspace.
-// Workspace layout: [scratch plane][counters][trash row][slowness chunk x ldp
-// doubles][partials chunk x nw x ldp floats].
+// Workspace layout: [status word][scratch plane][counters][trash row]
+// [slowness chunk x ldp doubles][partials chunk x nw x ldp floats].
 int run_extrap(const float2* src, float2* dst, const float* vel, const double* omega,
                const float2* tab, const mig_table_desc* d, int nx, int nw, int nsteps,
                double* rows, void* ws, size_t ws_bytes, hipStream_t s, const Tuning& tn)
 {
     const int ldp = row_stride(nx);
-    const size_t head = plane_bytes(nx, nw) + kCounterBytes + (size_t)ldp * sizeof(float);
+    const size_t head = extrap_head_bytes(nx, nw);
     const size_t sb = step_bytes(nx, nw, rows != nullptr);
     if (!ws || ws_bytes < head + sb) return MIG_E_WORKSPACE;
     size_t fit = (ws_bytes - head) / sb;
@@ -127,11 +172,14 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
     if (chunk > kMaxChunk) chunk = kMaxChunk;
     // ldp is a multiple of 256, so every region below stays 1 KB-aligned.
     char* base = static_cast<char*>(ws);
+    int* status = reinterpret_cast<int*>(base);
+    base += kStatusBytes;
     float2* scratch = reinterpret_cast<float2*>(base);
     int* cnt = reinterpret_cast<int*>(base + plane_bytes(nx, nw));
     float* trash = reinterpret_cast<float*>(base + plane_bytes(nx, nw) + kCounterBytes);
-    double* slow = reinterpret_cast<double*>(base + head);
-    float* part = reinterpret_cast<float*>(base + head + (size_t)chunk * ldp * sizeof(double));
+    double* slow = reinterpret_cast<double*>(static_cast<char*>(ws) + head);
+    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + head +
+                                           (size_t)chunk * ldp * sizeof(double));
 
     const int M = (d->ntaps - 1) / 2;
     const int kind = extrap_kernel_kind(nx, M);
@@ -151,6 +199,8 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
     a.tab = tab;
     a.trash = trash;
     a.progress = cnt + kMaxBlocks;
+    a.status = status;
+    set_reducer_limits(a, tn);
     a.nsec = 1;
     a.nitems = nitems;
     a.nk = d->nk;
@@ -185,7 +235,9 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
             a.ntasks = 0;
             a.nred = 0;
         }
-        // the slowness launch also zeroes the block counters
+        // the slowness launch also zeroes the block counters, and the status
+        // word at the first chunk of the call
+        a.reset_status = c0 == 0 ? 1 : 0;
         int rc = launch_slowness(a, cs, ldp, flag_distance(kind), s);
         if (rc == MIG_OK) {
             if (kind == 0) rc = launch_general(a, nx, s);
@@ -254,7 +306,7 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
                 char* base, BatchPlan& P)
 {
     const int M = (d->ntaps - 1) / 2;
-    size_t off = 0;
+    size_t off = kStatusBytes;  // [status word] first, as for a single section
     int max_ldp = 0;
     for (int i = 0; i < nsec; ++i) max_ldp = row_stride(secs[i].nx) > max_ldp ? row_stride(secs[i].nx) : max_ldp;
     P.trash_off = bump(off, (size_t)max_ldp * sizeof(float));
@@ -293,7 +345,7 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
     for (int k = 0; k < 4; ++k) {
         BatchPlan::Group& g = P.group[k];
         if (g.secs.empty()) continue;
-        g.cnt_off = bump(off, (size_t)(g.ncnt + 1) * sizeof(int));  // + the publish count
+        g.cnt_off = bump(off, (size_t)(g.ncnt + 2) * sizeof(int));  // + publish count, abandon
         for (SecDev& S : g.secs)
             S.cnt = reinterpret_cast<int*>(base ? base + g.cnt_off + (size_t)S.cnt * sizeof(int) : nullptr);
         // Items: longest first (depth steps x points), so the tail of the
@@ -360,6 +412,30 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
     char* base = static_cast<char*>(ws);
     plan_batch(secs, nsec, d, tn, base, P);
     if (!ws || ws_bytes < P.bytes) return MIG_E_WORKSPACE;
+    // The descriptors of every kernel variant go to the workspace in one copy
+    // from a host buffer owned by this call; the call waits for that copy
+    // (and so for the stream's earlier work) before the buffer goes away.
+    size_t lo = 0, hi = 0;
+    for (const BatchPlan::Group& g : P.group)
+        if (!g.secs.empty()) {
+            lo = lo == 0 && hi == 0 ? g.desc_off : (g.desc_off < lo ? g.desc_off : lo);
+            hi = g.desc_off + g.desc_bytes > hi ? g.desc_off + g.desc_bytes : hi;
+        }
+    if (hi > lo) {
+        std::vector<char> host(hi - lo, 0);
+        for (const BatchPlan::Group& g : P.group) {
+            if (g.secs.empty()) continue;
+            char* o = host.data() + (g.desc_off - lo);
+            memcpy(o, g.secs.data(), g.secs.size() * sizeof(SecDev));
+            o += g.secs.size() * sizeof(SecDev);
+            memcpy(o, g.items.data(), g.items.size() * sizeof(ItemDev));
+            o += g.items.size() * sizeof(ItemDev);
+            memcpy(o, g.tasks.data(), g.tasks.size() * sizeof(TaskDev));
+        }
+        if (hipMemcpyAsync(base + lo, host.data(), hi - lo, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MIG_E_DEVICE;
+    }
     for (int i = 0; i < nsec; ++i) {
         int rc = launch_image(reinterpret_cast<const float2*>(secs[i].data), secs[i].image,
                               secs[i].nx, secs[i].nw, s);
@@ -368,19 +444,11 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
     const int M = (d->ntaps - 1) / 2;
     // wide sections first: their items are the longest
     const int kinds[4] = {2, 3, 1, 0};
+    bool first = true;
     for (int kk = 0; kk < 4; ++kk) {
         BatchPlan::Group& g = P.group[kinds[kk]];
         if (g.secs.empty()) continue;
-        std::vector<char> host(g.desc_bytes);
-        size_t o = 0;
-        memcpy(host.data() + o, g.secs.data(), g.secs.size() * sizeof(SecDev));
-        o += g.secs.size() * sizeof(SecDev);
-        memcpy(host.data() + o, g.items.data(), g.items.size() * sizeof(ItemDev));
-        o += g.items.size() * sizeof(ItemDev);
-        memcpy(host.data() + o, g.tasks.data(), g.tasks.size() * sizeof(TaskDev));
         char* dev = base + g.desc_off;
-        if (hipMemcpyAsync(dev, host.data(), g.desc_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-            return MIG_E_DEVICE;
         BatchArgs a = {};
         a.secs = reinterpret_cast<const SecDev*>(dev);
         a.items = reinterpret_cast<const ItemDev*>(dev + g.secs.size() * sizeof(SecDev));
@@ -389,6 +457,10 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
         a.tab = tab;
         a.trash = reinterpret_cast<float*>(base + P.trash_off);
         a.progress = reinterpret_cast<int*>(base + g.cnt_off) + g.ncnt;
+        a.status = reinterpret_cast<int*>(base);
+        a.reset_status = first ? 1 : 0;
+        first = false;
+        set_reducer_limits(a, tn);
         a.nsec = (int)g.secs.size();
         a.nitems = (int)g.items.size();
         a.ntasks = (int)g.tasks.size();
@@ -496,15 +568,24 @@ MIG_API size_t mig_workspace_size(int32_t nx, int32_t nsteps, int32_t nw, const 
 {
     if (!desc_valid(d) || !sizes_ok(nx, nw) || nsteps < 0) return 0;
     size_t steps = nsteps > 0 ? (size_t)nsteps : 1;
-    return plane_bytes(nx, nw) + kCounterBytes + (size_t)row_stride(nx) * sizeof(float) +
-           steps * step_bytes(nx, nw, true);
+    return extrap_head_bytes(nx, nw) + steps * step_bytes(nx, nw, true);
 }
 
 MIG_API size_t mig_workspace_min_size(int32_t nx, int32_t nw, const mig_table_desc* d)
 {
     if (!desc_valid(d) || !sizes_ok(nx, nw)) return 0;
-    return plane_bytes(nx, nw) + kCounterBytes + (size_t)row_stride(nx) * sizeof(float) +
-           step_bytes(nx, nw, true);
+    return extrap_head_bytes(nx, nw) + step_bytes(nx, nw, true);
+}
+
+MIG_API int mig_workspace_status(const void* ws, void* stream)
+{
+    if (!ws) return MIG_E_ARG;
+    hipStream_t s = as_stream(stream);
+    int st = 0;
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(&st, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return MIG_E_DEVICE;
+    return st == 0 ? MIG_OK : MIG_E_DEVICE;
 }
 
 MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out, const float* vel,
@@ -523,12 +604,12 @@ MIG_API int mig_extrapolate(const mig_c64* wf_in, mig_c64* wf_out, const float* 
     if (nsteps == 0) {
         if (wf_out && hipMemcpyAsync(dst, src, pl, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return MIG_E_DEVICE;
-        return MIG_OK;
+        return clear_status(ws, ws_bytes, s);
     }
     if (ws && (overlap(ws, ws_bytes, wf_in, pl) || (wf_out && overlap(ws, ws_bytes, wf_out, pl))))
         return MIG_E_ARG;
     return run_extrap(src, dst, vel, omega, reinterpret_cast<const float2*>(tab32), d, nx, nw,
-                      nsteps, rows, ws, ws_bytes, s, Tuning{0, 0});
+                      nsteps, rows, ws, ws_bytes, s, Tuning{});
 }
 
 MIG_API int mig_image(const mig_c64* wf, double* row, int32_t nx, int32_t nw, void* stream)
@@ -546,19 +627,20 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel, const double* ome
         return MIG_E_ARG;
     hipStream_t s = as_stream(stream);
     int rc = launch_image(reinterpret_cast<const float2*>(data), image, nx, nw, s);
-    if (rc != MIG_OK || nz == 1) return rc;
+    if (rc != MIG_OK) return rc;
+    if (nz == 1) return clear_status(ws, ws_bytes, s);
     const size_t pl = (size_t)nx * nw * sizeof(mig_c64);
     if (ws && overlap(ws, ws_bytes, data, pl)) return MIG_E_ARG;
     return run_extrap(reinterpret_cast<const float2*>(data), nullptr, vel, omega,
                       reinterpret_cast<const float2*>(tab32), d, nx, nw, nz - 1, image + nx, ws,
-                      ws_bytes, s, Tuning{0, 0});
+                      ws_bytes, s, Tuning{});
 }
 
 MIG_API size_t mig_batch_workspace_size(const mig_section* secs, int32_t nsec,
                                         const mig_table_desc* d, const mig_tuning* tune)
 {
-    if (!desc_valid(d) || !sections_ok(secs, nsec)) return 0;
-    Tuning tn{tune ? tune->omegas_per_group : 0, tune ? tune->reducers : 0};
+    if (!desc_valid(d) || !sections_ok(secs, nsec) || !tuning_valid(tune)) return 0;
+    Tuning tn = tuning_of(tune);
     BatchPlan P;
     plan_batch(secs, nsec, d, tn, nullptr, P);
     return P.bytes;
@@ -568,15 +650,13 @@ MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec, const mig
                                 const mig_table_desc* d, const mig_tuning* tune, void* ws,
                                 size_t ws_bytes, void* stream)
 {
-    if (!desc_valid(d) || !tab32 || !sections_ok(secs, nsec)) return MIG_E_ARG;
-    if (tune && (tune->omegas_per_group < 0 || tune->reducers < 0 || tune->reserved[0] != 0 ||
-                 tune->reserved[1] != 0))
+    if (!desc_valid(d) || !tab32 || !sections_ok(secs, nsec) || !tuning_valid(tune))
         return MIG_E_ARG;
     for (int i = 0; i < nsec; ++i) {
         const size_t pl = (size_t)secs[i].nx * secs[i].nw * sizeof(mig_c64);
         if (ws && overlap(ws, ws_bytes, secs[i].data, pl)) return MIG_E_ARG;
     }
-    Tuning tn{tune ? tune->omegas_per_group : 0, tune ? tune->reducers : 0};
+    Tuning tn = tuning_of(tune);
     return run_batch(secs, nsec, reinterpret_cast<const float2*>(tab32), d, tn, ws, ws_bytes,
                      as_stream(stream));
 }

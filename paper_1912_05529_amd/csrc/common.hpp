@@ -15,8 +15,16 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kPublish = 32;
 // Reducers poll a block counter with this s_sleep argument (x 64 cycles).
 constexpr int kPollSleep = 127;
-// Reducers give up (and write NaN rows) after this long without progress.
+// Default reducer stall limit: a reducer that sees no publish anywhere in the
+// launch for this long gives up for the whole launch (NaN rows, status set).
 constexpr unsigned long long kStallTicks = 20ull * 100000000ull;  // 20 s at 100 MHz
+// The device clock read by wall_clock64() runs at 100 MHz.
+constexpr unsigned long long kWallTicksPerUs = 100ull;
+
+// Sticky status word at the head of a workspace (kStatusBytes reserved):
+// 0, or kStatusAbandoned once a reducer gave up waiting for a block.
+constexpr size_t kStatusBytes = 256;
+constexpr int kStatusAbandoned = 1;
 
 // One section as the depth-stepping kernels see it (device pointers).
 struct SecDev {
@@ -55,7 +63,14 @@ struct BatchArgs {
     const TaskDev* tasks;
     const float2* tab;     // [nk][M+1] complex64 half-taps
     float* trash;          // [ldp_max] sink for partial rows of idle sub-groups
-    int* progress;         // publishes of the whole launch (reducers' stall clock)
+    // progress[0]: publishes of the whole launch (restarts the reducers'
+    // stall clock); progress[1]: abandon word, set by the first reducer that
+    // runs into the stall limit, after which no reducer of the launch waits
+    int* progress;
+    int* status;           // sticky status of the call (workspace head), or nullptr
+    unsigned long long stall_ticks;  // reducer stall limit (wall_clock64 ticks)
+    int reset_status;      // the slowness launch zeroes *status (first launch of a call)
+    int extra_wait;        // test hook: reducers wait for nprod + extra_wait publishes
     int nsec, nitems, ntasks, nred;
     int rows;              // frequency workgroups write and publish partial rows
     int parts;             // x-parts per block (nsec == 1)
@@ -185,6 +200,8 @@ int launch_demigrate_reg(const AdjArgs& a, hipStream_t s);
 int launch_transform(const float* section, int nx, int nt, double dt, const double* omega,
                      int nw, float2* out, float* B, hipStream_t s);
 int launch_image(const float2* wf, double* row, int nx, int nw, hipStream_t s);
+// Zeroes a workspace's status word (calls that run no depth-stepping launch).
+int launch_clear_status(int* status, hipStream_t s);
 // Image rows of depth steps [s0, s1) of one section from its partial rows
 // ([step][nw][ldp] floats), after the depth-stepping launch.
 int launch_rows(const float* part, double* rows, int s0, int s1, int nx, int nw, int ldp,

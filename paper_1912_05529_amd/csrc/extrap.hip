@@ -37,8 +37,10 @@
 //     omega in increasing order in FP64, so images are run-to-run identical
 //     and the reduction overlaps the extrapolation; the last block of a plain
 //     launch is summed after it (k_rows) by the whole GPU.  Frequency
-//     workgroups never wait on anyone; reducer waits are bounded (kStallTicks
-//     without any publish in the launch writes NaN rows instead of hanging).
+//     workgroups never wait on anyone; reducer waits are bounded: after
+//     kStallTicks (or the caller's limit) without any publish in the launch,
+//     the launch is abandoned as a whole -- every remaining task writes NaN
+//     rows without waiting -- and the call's status word says so.
 #include "common.hpp"
 
 namespace mig {
@@ -179,7 +181,13 @@ __global__ void k_slowness(BatchArgs a, int dist)
     if (S.cnt && blockIdx.x == 0)
         for (int i = threadIdx.x; i < (S.nsteps + kPublish - 1) / kPublish; i += blockDim.x)
             S.cnt[i] = 0;
-    if (a.progress && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.progress = 0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        if (a.progress) {
+            a.progress[0] = 0;
+            a.progress[1] = 0;
+        }
+        if (a.status && a.reset_status) *a.status = 0;
+    }
     double* slow = const_cast<double*>(S.slow);
     const size_t total = (size_t)S.nsteps * S.ldp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -212,6 +220,46 @@ __device__ __forceinline__ void publish_block(const BatchArgs& a, const SecDev& 
     }
 }
 
+__device__ __forceinline__ int load_relaxed(int* p)
+{
+    return __hip_atomic_load(as_global(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 of a reducer: wait until block T.block of section S is published
+// by all its frequency workgroups.  Returns false when the launch has been
+// abandoned: by this reducer, after kStallTicks (or the caller's limit)
+// without any publish in the launch, or by another reducer before.  The
+// first reducer to give up sets the launch's abandon word and the call's
+// status word; every later wait of the launch returns at once.
+__device__ bool wait_block(const BatchArgs& a, const SecDev& S, int block)
+{
+    int* const abandon = a.progress + 1;
+    const int need = S.nprod + a.extra_wait;
+    int v, last = -1, seen = -1;
+    unsigned long long t0 = wall_clock64();
+    while ((v = load_relaxed(S.cnt + block)) < need) {
+        if (load_relaxed(abandon) != 0) return false;
+        // the stall clock restarts whenever the block's counter or the
+        // launch's publish count moves: a section whose items start late in
+        // a long batch is waited for, a launch that stops is not
+        const int g = load_relaxed(a.progress);
+        const unsigned long long now = wall_clock64();
+        if (v != last || g != seen) {
+            last = v;
+            seen = g;
+            t0 = now;
+        } else if (now - t0 > a.stall_ticks) {
+            __hip_atomic_store(as_global(abandon), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.status)
+                __hip_atomic_store(as_global(a.status), kStatusAbandoned, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(kPollSleep);
+    }
+    return true;
+}
+
 // Reducer workgroup q of a.nred: tasks q, q + nred, ... (ordered block-major
 // across sections, i.e. in production order).  One wait and one acquire per
 // task: an acquire invalidates the L2 of the reducer's XCD, which the
@@ -226,27 +274,9 @@ __device__ void reduce_role(const BatchArgs& a, int q, int* flag)
         const SecDev S = sec_of(a, T.sec);
         if (T.block * kPublish >= S.nsteps) continue;  // no such block (uniform)
         if (threadIdx.x == 0) {
-            // the stall clock restarts whenever the block's counter or the
-            // launch's publish count moves: a section whose items start late
-            // in a long batch is waited for, a launch that stops is not
-            int v, last = -1, seen = -1;
-            unsigned long long t0 = wall_clock64();
-            while ((v = __hip_atomic_load(as_global(S.cnt + T.block), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT)) < S.nprod) {
-                const int g = __hip_atomic_load(as_global(a.progress), __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                unsigned long long now = wall_clock64();
-                if (v != last || g != seen) {
-                    last = v;
-                    seen = g;
-                    t0 = now;
-                } else if (now - t0 > kStallTicks) {
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(kPollSleep);
-            }
+            const bool ok = wait_block(a, S, T.block);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            *flag = v >= S.nprod ? 1 : 0;
+            *flag = ok ? 1 : 0;
         }
         __syncthreads();
         const bool ok = *flag != 0;
@@ -754,6 +784,16 @@ int launch_rows(const float* part, double* rows, int s0, int s1, int nx, int nw,
     if (s1 <= s0) return MIG_OK;
     dim3 grid((nx + 63) / 64, s1 - s0);
     hipLaunchKernelGGL(k_rows, grid, dim3(64), 0, s, part, rows, s0, nx, nw, ldp);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+namespace {
+__global__ void k_clear_status(int* status) { *status = 0; }
+}  // namespace
+
+int launch_clear_status(int* status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, status);
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 

@@ -57,7 +57,10 @@ class CTuning(C.Structure):
     """ctypes mirror of ``mig_tuning``."""
 
     _fields_ = [("omegas_per_group", C.c_int32), ("reducers", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("stall_limit_us", C.c_int32), ("flags", C.c_int32)]
+
+
+MIG_TUNE_FORCE_STALL = 1
 
 
 def cdesc(d) -> CDesc:
@@ -86,6 +89,7 @@ def lib():
         "mig_table_index": ([P, P, D, i32, i32, i32, P, P], C.c_int),
         "mig_workspace_size": ([i32, i32, i32, D], sz),
         "mig_workspace_min_size": ([i32, i32, D], sz),
+        "mig_workspace_status": ([P, P], C.c_int),
         "mig_extrapolate": ([P, P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
         "mig_image": ([P, P, i32, i32, P], C.c_int),
         "mig_migrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
@@ -191,6 +195,17 @@ def workspace_min_size(nx, nw, desc) -> int:
     return int(lib().mig_workspace_min_size(nx, nw, C.byref(cd)))
 
 
+def workspace_status(ws) -> int:
+    """Status of the last depth-stepping call on workspace ``ws`` (synchronizes
+    the current stream): MIG_OK, or MIG_E_DEVICE if a reduction was abandoned."""
+    return int(lib().mig_workspace_status(_p(ws), _stream()))
+
+
+def check_workspace(ws, what="depth stepping"):
+    """Raises MigError unless the last call on ``ws`` formed every image row."""
+    _check(workspace_status(ws), what)
+
+
 def kernel_kind(nx, ntaps) -> int:
     return int(lib().mig_kernel_kind(nx, ntaps))
 
@@ -291,6 +306,8 @@ def _tuning(tune):
     t = CTuning()
     t.omegas_per_group = int(tune.get("omegas_per_group", 0))
     t.reducers = int(tune.get("reducers", 0))
+    t.stall_limit_us = int(tune.get("stall_limit_us", 0))
+    t.flags = int(tune.get("flags", 0))
     return C.byref(t)
 
 

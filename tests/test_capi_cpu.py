@@ -72,6 +72,23 @@ def test_host_validation_rejects_bad_arguments(L):
     assert L.mig_design_table(C.byref(big), fake, None, None, None, fake, 1 << 30, None) == -1
     small = mig.cdesc(_desc())
     assert L.mig_design_table(C.byref(small), fake, None, None, None, fake, 16, None) == -4
+    # status query without a workspace
+    assert L.mig_workspace_status(None, None) == -1
+
+
+def test_batched_tuning_is_validated_on_the_host(L):
+    from paper_1912_05529_amd import mig
+    fake = C.c_void_p(4096)
+    d = mig.cdesc(_desc())
+    sec = (mig.CSection * 1)()
+    sec[0] = mig.CSection(4096, 8192, 12288, 16384, 64, 8, 4, 0)
+    ok = mig.CTuning(0, 0, 0, 0)
+    assert L.mig_batch_workspace_size(sec, 1, C.byref(d), C.byref(ok)) > 0
+    for bad in (mig.CTuning(-1, 0, 0, 0), mig.CTuning(0, -2, 0, 0), mig.CTuning(0, 0, -5, 0),
+                mig.CTuning(0, 0, 0, 2)):
+        assert L.mig_batch_workspace_size(sec, 1, C.byref(d), C.byref(bad)) == 0
+        assert L.mig_migrate_batched(sec, 1, fake, C.byref(d), C.byref(bad), fake, 1 << 30,
+                                     None) == -1
 
 
 def test_workspace_sizes_and_kernel_kinds(L):
@@ -79,11 +96,12 @@ def test_workspace_sizes_and_kernel_kinds(L):
     d = _desc(ntaps=35, nk=2048)
     full = mig.workspace_size(1024, 511, 200, d)
     one = mig.workspace_min_size(1024, 200, d)
-    plane = 1024 * 200 * 8 + 16384 + 1024 * 4  # scratch plane + block counters + sink row
+    # status word + scratch plane + block counters + sink row
+    plane = 256 + 1024 * 200 * 8 + 16384 + 1024 * 4
     step = 1024 * 8 + 200 * 1024 * 4          # slowness row + partial rows
     assert one == plane + step
     assert full == plane + 511 * step
-    plane_1000 = (1000 * 7 * 8 + 255) // 256 * 256 + 16384 + 1024 * 4
+    plane_1000 = 256 + (1000 * 7 * 8 + 255) // 256 * 256 + 16384 + 1024 * 4
     assert mig.workspace_size(1000, 3, 7, d) == plane_1000 + 3 * (1024 * 8 + 7 * 1024 * 4)
     assert mig.kernel_kind(1024, 35) == 1
     assert mig.kernel_kind(1025, 35) == 3

@@ -1,15 +1,18 @@
 """3-D extension through the C ABI: 2-D table design and migration of volumes
 against the FP64 oracle.
 
-Tolerances.  The table is compared as the 2-D sections' tables are: within
-four times the oracle's own sensitivity to 1-ulp changes of its inputs (the
-WLS map is ill-conditioned).  Wavefields are FP32: each depth step rounds a
-sum of (2M+1)^2 products, so the error relative to the plane's largest value
-grows about linearly with the number of steps; the bound used is
-8e-7 * (steps + 1) * NU of that largest value (NU = unique coefficients), and
-images (FP64 sums of FP32 values) are held to the same bound relative to
-their largest value.  Integer decisions (table entries) are taken in FP64 on
-both sides, so they agree exactly.
+Tolerances.  The GPU's FP64 table design must match the oracle's to 1e-10
+relative (the 2-D reweighting is gentle, so the design map is well
+conditioned: the oracle's own 1-ulp sensitivity is printed beside it).
+Wavefields are FP32: each depth step rounds a sum of (2M+1)^2 products, so
+the error relative to the plane's largest value grows about linearly with
+the number of steps; the bound used is 8e-7 * (steps + 1) * NU of that
+largest value (NU = unique coefficients), and images (FP64 sums of FP32
+values) are held to the same bound relative to their largest value.  Where
+the GPU runs with its own table and the oracle with its own, the table bound
+(1e-10, against FP32 rounding of the taps of 6e-8 that the path bound already
+covers) adds nothing measurable.  Integer decisions (table entries) are taken
+in FP64 on both sides, so they agree exactly.
 """
 import dataclasses
 
@@ -78,9 +81,8 @@ def test_design2d_matches_oracle(which, tables2d, cfg5_desc):
     t64 = g["tab64"].cpu().numpy()
     err = np.abs(t64 - ot).max() / np.abs(ot).max()
     sens = _ulp_sensitivity_2d(desc, ot)
-    tol = 4.0 * sens + 1e-12
+    tol = 1e-10
     print("%s 2-D table max rel diff %.3e; oracle 1-ulp sensitivity %.3e" % (which, err, sens))
-    assert tol < 6e-8
     assert err <= tol
     assert np.abs(g["maxgain"].cpu().numpy() - omg).max() <= tol
     assert np.abs(g["passerr"].cpu().numpy() - ope).max() <= tol
@@ -126,10 +128,17 @@ def test_migrate3d_matches_oracle(nx, ny, nz, nw, ntaps, layered, wpg):
     _check_volume(vol, ot, tab32, wpg)
 
 
+def _tables_agree(ot, g):
+    err = np.abs(g["tab64"].cpu().numpy() - ot).max() / np.abs(ot).max()
+    assert err <= 1e-10, err
+
+
 def test_point_scatterer_focuses_and_matches_oracle(tables2d):
+    """GPU with its own table, oracle with its own."""
     vol = synth.point_scatterer_3d()
     (ot, _, _, _), g = tables2d(vol.desc)
-    img, _ = _check_volume(vol, g["tab64"].cpu().numpy(), g["tab32"])
+    _tables_agree(ot, g)
+    img, _ = _check_volume(vol, ot, g["tab32"])
     im = img.cpu().numpy()
     k, x, y = np.unravel_index(np.argmax(np.abs(im)), im.shape)
     e = vol.extra
@@ -169,12 +178,14 @@ def test_single_depth_is_image_of_data():
 
 def test_config5_full_size_first_steps_match_oracle(tables2d, cfg5_desc):
     """Full lateral size and frequency count, in the launch configuration the
-    benchmark uses (library-chosen grouping), over the first 4 depth slices."""
+    benchmark uses (library-chosen grouping), over the first 4 depth slices;
+    GPU with its own table, oracle with its own."""
     vol = synth.config5()
     vol.vel = np.ascontiguousarray(vol.vel[:4])
     vol.nz = 4
     (ot, _, _, _), g = tables2d(vol.desc)
-    _check_volume(vol, g["tab64"].cpu().numpy(), g["tab32"])
+    _tables_agree(ot, g)
+    _check_volume(vol, ot, g["tab32"])
 
 
 def test_error_paths():

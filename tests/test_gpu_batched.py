@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_1912_05529_amd import mig, synth
-from gpu_helpers import data64, dev, rel_l2, upload
+from gpu_helpers import assert_rows_close, data64, dev, rel_l2, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -81,6 +81,7 @@ def test_batched_matches_oracle(mixed):
     for s, g in zip(secs, got):
         ref = oracle.migrate(desc, ot, s.omega, s.vel, data64(s))
         assert rel_l2(g, ref) <= 1e-5, s.name
+        assert_rows_close(g, ref, 1e-5, "batched " + s.name)
 
 
 def test_batched_workspace_and_argument_errors(mixed):
@@ -143,6 +144,37 @@ def test_config3_full_batch_matches_plain_and_oracle():
     for i in small:
         s = secs[i]
         ref = oracle.migrate(desc, ot, s.omega, s.vel, data64(s))
-        err = rel_l2(batch[i]["image"].cpu().numpy(), ref)
+        got = batch[i]["image"].cpu().numpy()
+        err = rel_l2(got, ref)
         print("  section %d nx=%d nz=%d nw=%d: rel L2 %.2e" % (i, s.nx, s.nz, s.nw, err), flush=True)
         assert err <= 1e-4
+        assert_rows_close(got, ref, 1e-4, "config3 section %d" % i)
+
+
+def test_stalled_reduction_is_reported_and_cleared(mixed):
+    """Failure path of the in-launch reduction, forced from the host: with
+    MIG_TUNE_FORCE_STALL the reducers wait for one publish more than the
+    frequency workgroups make; the first to reach the (short) stall limit
+    abandons the launch, every task writes NaN rows without waiting, every
+    kernel ends, and the workspace status reports the failure.  The next call
+    on the same workspace starts from a clean status."""
+    secs, desc, tab = mixed
+    batch = [dict(upload(s)) for s in secs[:3]]
+    stall = {"stall_limit_us": 2000, "flags": mig.MIG_TUNE_FORCE_STALL, "reducers": 8}
+    n = max(mig.batch_workspace_size(batch, desc, stall), mig.batch_workspace_size(batch, desc))
+    ws = torch.empty(n, dtype=torch.uint8, device=dev())
+    mig.migrate_batched(batch, tab["tab32"], desc, tune=stall, ws=ws)
+    assert mig.workspace_status(ws) == mig.MIG_E_DEVICE
+    with pytest.raises(mig.MigError):
+        mig.check_workspace(ws)
+    for b in batch:
+        img = b["image"]
+        assert torch.isfinite(img[0]).all()          # row 0: image of the data
+        if img.shape[0] > 1:
+            assert torch.isnan(img[1:]).all()
+    mig.migrate_batched(batch, tab["tab32"], desc, ws=ws)
+    assert mig.workspace_status(ws) == mig.MIG_OK
+    for s, b in zip(secs[:3], batch):
+        t = upload(s)
+        ref = mig.migrate(t["data"], t["vel"], t["omega"], tab["tab32"], desc)
+        assert torch.equal(b["image"], ref)

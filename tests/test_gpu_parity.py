@@ -2,12 +2,12 @@
 
 Tolerances
   * table design (FP64 on both sides, same formulas, same accumulation order;
-    only libm vs device cos/sin/exp/hypot differ in the last bit).  The
-    reweighting passes multiply weights by 1 + (|H|-1)/tau with tau = 1e-4, a
-    gain of 1e4, so the design map itself is ill-conditioned: a 1-ulp change
-    of dx, dz or tau moves the oracle's own table by up to ~1e-8 (config 2).
-    The bound is therefore 4x the oracle's measured 1-ulp sensitivity (plus
-    1e-12), which stays below the FP32 rounding of the taps (6e-8);
+    only libm vs device cos/sin/exp/sqrt differ in the last bit): 1e-10
+    relative.  The reweighting passes multiply weights by
+    1 + beta (|H|-1)/tau; with tau = 5e-4 a 1-ulp change of dx, dz or tau
+    moves the oracle's own table by at most ~2e-11, so last-bit differences
+    of the transcendental functions stay well inside the bound (the test
+    prints that sensitivity next to the measured difference);
   * table look-up: bit-exact (same IEEE-double operation sequence);
   * FP32 extrapolation vs FP64 oracle: relative L2 <= 1e-5 after a few steps
     (FP32 taps and arithmetic, ~1e-7 per operation, ~2N operations per output
@@ -23,7 +23,7 @@ import torch
 
 import oracle
 from paper_1912_05529_amd import mig, synth
-from gpu_helpers import data64, dev, rel_l2, upload
+from gpu_helpers import assert_rows_close, data64, dev, rel_l2, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +57,8 @@ def test_design_table_matches_oracle(which, tables, cfg1, cfg2_model):
     t64 = g["tab64"].cpu().numpy()
     err = np.abs(t64 - ot).max() / np.abs(ot).max()
     sens = _ulp_sensitivity(desc, ot)
-    tol = 4.0 * sens + 1e-12
+    tol = 1e-10
     print("%s table max rel diff %.3e; oracle 1-ulp sensitivity %.3e" % (which, err, sens))
-    assert tol < 6e-8
     assert err <= tol
     assert np.abs(g["maxgain"].cpu().numpy() - omg).max() <= tol
     assert np.abs(g["passerr"].cpu().numpy() - ope).max() <= tol
@@ -140,6 +139,7 @@ def test_migrate_config1_matches_oracle_and_focuses(cfg1, cfg1_table, tables):
     err = rel_l2(img, ref)
     print("config1 image rel L2 %.3e" % err)
     assert err <= 1e-4
+    assert_rows_close(img, ref, 1e-4, "config1 image")
     iz, ix = np.unravel_index(np.argmax(np.abs(img)), img.shape)
     assert abs(iz - cfg1.extra["iz0"]) <= 1 and abs(ix - cfg1.extra["ix0"]) <= 1
 
@@ -156,9 +156,14 @@ def test_migrate_config2_full_matches_oracle(cfg2_full, tables):
     img = mig.migrate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc).cpu().numpy()
     ref = oracle.migrate(sec.desc, ot, sec.omega, sec.vel, data64(sec))
     err = rel_l2(img, ref)
-    rows = [rel_l2(img[k], ref[k]) for k in (1, 128, 256, 511)]
-    print("config2 image rel L2 %.3e; rows 1/128/256/511: %s" % (err, rows))
+    print("config2 image rel L2 %.3e" % err)
     assert err <= 1e-4
+    assert_rows_close(img, ref, 1e-4, "config2 image")
+    # the rows through the 4800 m/s body, element by element on their own scale
+    body = np.nonzero((sec.vel * 2.0 == 4800.0).any(axis=1))[0]
+    assert body.size > 0
+    assert_rows_close(img[body], ref[body], 1e-4, "config2 rows crossing the body",
+                      energy_floor=0.0)
 
 
 def test_migrate_is_deterministic_and_chunking_is_exact(tables):
@@ -211,9 +216,52 @@ def test_fused_reduction_rows_match_oracle(nx, nw, nsteps, ntaps, tables):
           flush=True)
     t = upload(sec)
     vel = t["vel"][:nsteps].contiguous()
+    ws = torch.empty(mig.workspace_size(nx, nsteps, nw, sec.desc), dtype=torch.uint8,
+                     device=dev())
     _, rows = mig.extrapolate(t["data"], vel, t["omega"], g["tab32"], sec.desc, nsteps,
-                              want_plane=False)
+                              want_plane=False, ws=ws)
+    assert mig.workspace_status(ws) == mig.MIG_OK
     r = rows.cpu().numpy()
     assert np.isfinite(r).all()
     _, ref = oracle.extrapolate(sec.desc, ot, sec.omega, sec.vel[:nsteps], data64(sec), nsteps)
     assert rel_l2(r, ref) <= 1e-5
+
+
+def _bad_velocity_case(seed, nx, nz, nw):
+    """Layered section whose velocity holds values that are not > 0: NaN, +0,
+    -0, negative numbers, and a whole NaN row; each selects table entry 0."""
+    sec = synth.random_case(seed, nx, nz, nw, ntaps=35, nk=256)
+    v = sec.vel.copy()
+    v[1, 3:40] = np.nan
+    v[2, :] = np.nan
+    v[3, 10:20] = 0.0
+    v[3, 20:25] = -0.0
+    v[4, nx // 2:] = -1500.0
+    v[5, ::7] = np.nan
+    v[nz - 2, -5:] = -np.inf
+    sec.vel = v
+    return sec
+
+
+@pytest.mark.parametrize("nx,nw", [(300, 7), (1024, 5), (1300, 4), (2100, 3)])
+def test_non_positive_and_nan_velocity_select_entry_0(nx, nw, tables):
+    """The look-up contract (velocity not > 0 -> entry 0) through the
+    depth-stepping kernels of migrate, the adjoint and the batched form,
+    against the oracle (which makes the same choice explicitly)."""
+    sec = _bad_velocity_case(5000 + nx, nx, 12, nw)
+    (ot, _, _, _), g = tables(sec.desc)
+    print("bad velocity nx=%d kind=%d" % (nx, mig.kernel_kind(nx, 35)), flush=True)
+    t = upload(sec)
+    img = mig.migrate(t["data"], t["vel"], t["omega"], g["tab32"], sec.desc).cpu().numpy()
+    ref = oracle.migrate(sec.desc, ot, sec.omega, sec.vel, data64(sec))
+    assert_rows_close(img, ref, 1e-5, "migrate with bad velocities nx=%d" % nx)
+    b = [dict(t)]
+    mig.migrate_batched(b, g["tab32"], sec.desc)
+    torch.cuda.synchronize()
+    assert torch.equal(b[0]["image"].cpu(), torch.from_numpy(img))
+    rng = np.random.default_rng(nx)
+    m = rng.standard_normal((sec.nz, nx))
+    dem = mig.demigrate(torch.from_numpy(m).to(dev()), t["vel"], t["omega"], g["tab32"],
+                        sec.desc).cpu().numpy()
+    dref = oracle.demigrate(sec.desc, ot, sec.omega, sec.vel, m)
+    assert_rows_close(dem, dref, 1e-5, "demigrate with bad velocities nx=%d" % nx, axis=1)
