@@ -222,6 +222,32 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel,
                         void* stream);
 
 /*
+ * Allocation-free form of mig_migrate, for callers that cannot allocate device
+ * memory or hand over a workspace: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments and results
+ * as mig_migrate without ws/ws_bytes: the scratch (status word, intermediate
+ * plane, block counters, slowness rows, partial image rows) lives in a static
+ * device array of MIG_STATIC_SCRATCH_BYTES per GPU, created with the library's
+ * code object and held until the process ends.  The depth loop is split into
+ * as many chunks as that array needs (images bit-identical to mig_migrate).
+ * Calls nothing that allocates.
+ *   Returns MIG_E_WORKSPACE when one depth step does not fit
+ *   (mig_workspace_min_size(nx, nw, d) > MIG_STATIC_SCRATCH_BYTES, e.g.
+ *   nx * nw beyond about 8e6 points), MIG_E_ARG as mig_migrate.
+ *   Every call on a GPU uses that GPU's one array, which keeps the last call's
+ *   contents (each call clears what must start at zero): calls that overlap
+ *   on one GPU (other streams, other host threads) race and must be
+ *   serialized by the caller.  The reduction status of mig_workspace_status
+ *   is not reachable here: an abandoned reduction shows as NaN image rows.
+ */
+#define MIG_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+MIG_API int mig_migrate_noalloc(const mig_c64* data, const float* vel,
+                                const double* omega, const mig_c64* tab32,
+                                const mig_table_desc* d, int32_t nx,
+                                int32_t nz, int32_t nw, double* image,
+                                void* stream);
+
+/*
  * The step before the depth loop (Algorithm 1: transform of the section along
  * t; Sec. III): out[x][r] = sum_n section[x][n] exp(-i omega_r n dt), directly
  * at the given frequencies (they need not be FFT bins), so that t-x sections

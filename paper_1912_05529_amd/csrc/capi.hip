@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <vector>
 
@@ -174,7 +175,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
     char* base = static_cast<char*>(ws);
     int* status = reinterpret_cast<int*>(base);
     base += kStatusBytes;
-    float2* scratch = reinterpret_cast<float2*>(base);
+    float2* mid = reinterpret_cast<float2*>(base);
     int* cnt = reinterpret_cast<int*>(base + plane_bytes(nx, nw));
     float* trash = reinterpret_cast<float*>(base + plane_bytes(nx, nw) + kCounterBytes);
     double* slow = reinterpret_cast<double*>(static_cast<char*>(ws) + head);
@@ -215,7 +216,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
         a.one.win = cur;
         // Intermediate planes go to the scratch plane, in place: each workgroup
         // reads its whole frequency columns before writing them back.
-        a.one.wout = last ? dst : scratch;
+        a.one.wout = last ? dst : mid;
         a.one.vel = vel + (size_t)c0 * nx;
         a.one.nsteps = cs;
         a.one.rows = rows ? rows + (size_t)c0 * nx : nullptr;
@@ -245,7 +246,7 @@ int run_extrap(const float2* src, float2* dst, const float* vel, const double* o
         }
         if (rc == MIG_OK && rows) rc = launch_rows(part, a.one.rows, (nb - 1) * kPublish, cs, nx, nw, ldp, s);
         if (rc != MIG_OK) return rc;
-        cur = scratch;
+        cur = mid;
     }
     return MIG_OK;
 }
@@ -491,6 +492,31 @@ int run_batch(const mig_section* secs, int nsec, const float2* tab, const mig_ta
     return MIG_OK;
 }
 
+// Allocation-free form of mig_migrate: the workspace is a static device array,
+// one per GPU (the loader creates it with the code object), held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[MIG_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's static workspace, or nullptr.
+void* static_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -634,6 +660,21 @@ MIG_API int mig_migrate(const mig_c64* data, const float* vel, const double* ome
     return run_extrap(reinterpret_cast<const float2*>(data), nullptr, vel, omega,
                       reinterpret_cast<const float2*>(tab32), d, nx, nw, nz - 1, image + nx, ws,
                       ws_bytes, s, Tuning{});
+}
+
+MIG_API int mig_migrate_noalloc(const mig_c64* data, const float* vel, const double* omega,
+                                const mig_c64* tab32, const mig_table_desc* d, int32_t nx,
+                                int32_t nz, int32_t nw, double* image, void* stream)
+{
+    if (!desc_valid(d) || !data || !vel || !omega || !tab32 || !image || !sizes_ok(nx, nw) ||
+        nz < 1)
+        return MIG_E_ARG;
+    // at least one depth step (plus the plane between chunks) must fit
+    if (mig_workspace_min_size(nx, nw, d) > (size_t)MIG_STATIC_SCRATCH_BYTES) return MIG_E_WORKSPACE;
+    void* ws = static_scratch();
+    if (!ws) return MIG_E_DEVICE;
+    return mig_migrate(data, vel, omega, tab32, d, nx, nz, nw, image, ws,
+                       (size_t)MIG_STATIC_SCRATCH_BYTES, stream);
 }
 
 MIG_API size_t mig_batch_workspace_size(const mig_section* secs, int32_t nsec,

@@ -93,6 +93,7 @@ def lib():
         "mig_extrapolate": ([P, P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
         "mig_image": ([P, P, i32, i32, P], C.c_int),
         "mig_migrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
+        "mig_migrate_noalloc": ([P, P, P, P, D, i32, i32, i32, P, P], C.c_int),
         "mig_kernel_kind": ([i32, i32], C.c_int),
         "mig_transform_workspace_size": ([i32, i32], sz),
         "mig_transform_t": ([P, i32, i32, C.c_double, P, i32, P, P, sz, P], C.c_int),
@@ -278,6 +279,25 @@ def migrate(data, vel, omega, tab32, desc, ws=None, out=None):
     rc = lib().mig_migrate(_p(data), _p(vel), _p(omega), _p(tab32), C.byref(cd), nx, nz, nw,
                            _p(img), _p(ws), ws.numel(), _stream())
     _check(rc, "mig_migrate")
+    return img
+
+
+def migrate_noalloc(data, vel, omega, tab32, desc, out=None):
+    """Algorithm 1 end to end through the allocation-free entry point: the
+    library's static per-GPU workspace instead of a caller workspace."""
+    nx, nw = data.shape
+    nz = vel.shape[0]
+    _need(data, torch.complex64, (nx, nw), "data")
+    _need(vel, torch.float32, (nz, nx), "vel")
+    _need(omega, torch.float64, (nw,), "omega")
+    _need(tab32, torch.complex64, (desc.nk, (desc.ntaps - 1) // 2 + 1), "tab32")
+    img = out if out is not None else torch.empty((nz, nx), dtype=torch.float64,
+                                                  device=data.device)
+    _need(img, torch.float64, (nz, nx), "image")
+    cd = cdesc(desc)
+    rc = lib().mig_migrate_noalloc(_p(data), _p(vel), _p(omega), _p(tab32), C.byref(cd), nx, nz,
+                                   nw, _p(img), _stream())
+    _check(rc, "mig_migrate_noalloc")
     return img
 
 

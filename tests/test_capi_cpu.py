@@ -76,6 +76,23 @@ def test_host_validation_rejects_bad_arguments(L):
     assert L.mig_workspace_status(None, None) == -1
 
 
+def test_noalloc_entry_is_validated_on_the_host(L):
+    """The allocation-free call rejects bad arguments and sizes whose one depth
+    step does not fit its static workspace before touching the device."""
+    from paper_1912_05529_amd import mig
+    fake = C.c_void_p(4096)
+    good = mig.cdesc(_desc(ntaps=35, nk=2048))
+    inv = mig.cdesc(_desc(kmin=0.5, kmax=0.1))
+    assert L.mig_migrate_noalloc(fake, fake, fake, fake, C.byref(inv), 8, 4, 2, fake, None) == -1
+    assert L.mig_migrate_noalloc(None, fake, fake, fake, C.byref(good), 8, 4, 2, fake, None) == -1
+    assert L.mig_migrate_noalloc(fake, fake, fake, fake, C.byref(good), 8, 0, 2, fake, None) == -1
+    static = 64 * 1024 * 1024
+    assert mig.workspace_min_size(8192, 2048, _desc(ntaps=35, nk=2048)) > static
+    assert L.mig_migrate_noalloc(fake, fake, fake, fake, C.byref(good), 8192, 4, 2048, fake,
+                                 None) == -4
+    assert mig.workspace_min_size(1024, 200, _desc(ntaps=35, nk=2048)) < static
+
+
 def test_batched_tuning_is_validated_on_the_host(L):
     from paper_1912_05529_amd import mig
     fake = C.c_void_p(4096)
