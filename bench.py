@@ -341,7 +341,7 @@ def adjoint(torch, mig, synth, dev, args, ctx=None, profile=False):
     desc = sec.desc
     refl = torch.from_numpy(sec.extra["refl"]).to(dev)
     nz, nx = refl.shape
-    ws_a = torch.empty(max(mig.demigrate_workspace_size(nx, nz, desc), 1), dtype=torch.uint8,
+    ws_a = torch.empty(max(mig.demigrate_workspace_size(nx, nz, sec.nw, desc), 1), dtype=torch.uint8,
                        device=dev)
     d = torch.empty((nx, sec.nw), dtype=torch.complex64, device=dev)
     reps = max(1, args.steps // 4)

@@ -274,11 +274,19 @@ MIG_API int mig_transform_t(const float* section, int32_t nx, int32_t nt,
  *     data = Q_0,
  * where j(x, k) is the table entry of (omega_r, vel[k][x]).  FP32 complex
  * arithmetic, one workgroup per frequency walking the depth steps backwards.
+ * For nx <= 1024 and N <= 35 the step is the FIR with each point's own
+ * conjugated taps plus exact corrections where the velocity changes along x
+ * (at most 16 such points per row; otherwise, and for nk > 65536, a kernel
+ * that forms every product conj(h_j(y)[m]) q[y] runs instead); results agree
+ * to FP32 rounding either way and are run-to-run identical.
  *   image [nz][nx] float64 (in), vel [nz][nx] float32 (in; row nz-1 unused),
  *   omega [nw] float64 (in), tab32 [nk][M+1] complex64 (in),
- *   data  [nx][nw] complex64 (out), ws >= mig_demigrate_workspace_size bytes.
+ *   data  [nx][nw] complex64 (out), ws >= mig_demigrate_workspace_size bytes
+ *   (slowness rows, the change points of every row and their table entries
+ *   per frequency: about (nz-1)(8 ldp + 64 nw) bytes, ldp = nx rounded up to
+ *   256).
  */
-MIG_API size_t mig_demigrate_workspace_size(int32_t nx, int32_t nz,
+MIG_API size_t mig_demigrate_workspace_size(int32_t nx, int32_t nz, int32_t nw,
                                             const mig_table_desc* d);
 MIG_API int mig_demigrate(const double* image, const float* vel,
                           const double* omega, const mig_c64* tab32,

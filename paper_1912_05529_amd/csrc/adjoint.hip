@@ -7,11 +7,15 @@
 // where (S* i)[x][r] = i[x] and
 //     (E_k^H q)[x] = sum_{n=-M..M} conj(h_{j(x+n,k)}[|n|]) q[x+n]:
 // every point x+n contributes through the filter of that point.  A workgroup
-// owns one frequency for all depths (walking them backwards); per step it
-// forms g_m[y] = conj(h_{j(y)}[m]) q[y] for its points in LDS and gathers
-// out[x] = g_0[x] + sum_m (g_m[x-m] + g_m[x+m]).  The register-tap kernel
-// (nx <= 1024, N <= 35) does all taps in one LDS pass; the general kernel
-// handles any size a chunk of taps at a time.
+// owns one frequency for all depths (walking them backwards).  Three kernels:
+//   * folded (nx <= 1024, N <= 35, at most 16 lateral velocity changes per
+//     row): the Eq. (1) FIR with each point's own conjugated taps plus exact
+//     corrections around the points where the filter changes along x (see
+//     the derivation before k_demigrate_fold);
+//   * product (same sizes, any velocity; runs when some row has more change
+//     points): per step it forms g_m[y] = conj(h_{j(y)}[m]) q[y] for its
+//     points in LDS and gathers out[x] = g_0[x] + sum_m (g_m[x-m] + g_m[x+m]);
+//   * general (any size): the product form a chunk of taps at a time.
 #include "common.hpp"
 
 namespace mig {
@@ -81,7 +85,7 @@ __global__ void __launch_bounds__(512) k_demigrate(AdjArgs a)
 // them.  The plane Q never leaves registers; two barriers per depth step.
 // Taps come in two sets that alternate between steps: while a step runs on
 // one set, the other is refilled for the next step (only where the slowness
-// differs from the row two steps away, flag in the slowness sign bit), so the
+// of a row differs from the row below, flag in the slowness sign bit), so the
 // L2 latency of a refill hides behind a whole step.  The products live in
 // two LDS arrays, one for even and one for odd points, so that every LDS
 // access of a wave -- the stores of a thread's two points and each gather of
@@ -118,8 +122,8 @@ struct AdjLane {
     int y0, c0, c1;
     bool live0, live1;
     double ar;
-    double fl0, fl1;  // slowness of row k+1 (its flag: differs from row k-1)
-    double sv0, sv1;  // slowness of row k-1 (taps of step k-1)
+    double sn0, sn1;  // slowness of row k-1, flagged where it differs from row k
+    double sp0, sp1;  // the row before (k), flagged where it differs from row k+1
     double i0, i1;    // image row k
 };
 
@@ -133,22 +137,25 @@ __device__ __forceinline__ void adj_step(const AdjArgs& a, float2* G, int LP, Ad
     // everything issued during the previous step has arrived: the taps of
     // this step and the values prefetched for it
     wait_vmem();
+    // the other set was last loaded for step k+1: refill it for step k-1
+    // where row k-1 may differ from row k+1, i.e. where row k-1 differs from
+    // row k or row k from row k+1
     if (!first && k >= 1) {
-        if (slowness_changed(L.fl0))
+        if (slowness_changed(L.sn0) || slowness_changed(L.sp0))
             load_taps_adj<M>(ho0, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk,
-                                                                    slowness_value(L.sv0)) * (M + 1));
-        if (slowness_changed(L.fl1))
+                                                                    slowness_value(L.sn0)) * (M + 1));
+        if (slowness_changed(L.sn1) || slowness_changed(L.sp1))
             load_taps_adj<M>(ho1, a.tab + (size_t)index_of_slowness(L.ar, a.b, a.nk,
-                                                                    slowness_value(L.sv1)) * (M + 1));
+                                                                    slowness_value(L.sn1)) * (M + 1));
     }
     const double ci0 = L.i0, ci1 = L.i1;
     // prefetch for step k-1, branch-free (rows clamped; values past the top
     // are never used), so that nothing consumes them before the next step
     const int ks = k >= 2 ? k - 2 : 0, ki = k >= 1 ? k - 1 : 0;
-    L.fl0 = a.slow[(size_t)k * a.ldp + L.c0];
-    L.fl1 = a.slow[(size_t)k * a.ldp + L.c1];
-    L.sv0 = a.slow[(size_t)ks * a.ldp + L.c0];
-    L.sv1 = a.slow[(size_t)ks * a.ldp + L.c1];
+    L.sp0 = L.sn0;
+    L.sp1 = L.sn1;
+    L.sn0 = a.slow[(size_t)ks * a.ldp + L.c0];
+    L.sn1 = a.slow[(size_t)ks * a.ldp + L.c1];
     L.i0 = a.image[(size_t)ki * a.nx + L.c0];
     L.i1 = a.image[(size_t)ki * a.nx + L.c1];
     // E[m][H + p] = g_m[2p], O[m][H + p] = g_m[2p + 1]: thread t owns pair t.
@@ -215,6 +222,9 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
     extern __shared__ float4 smem4[];
     // [2][M+1][LP]: products at even and odd points, LP = pairs + 2 kH, zero
     // outside the points of the section
+    // launched beside the folded kernel: runs only when some row has more
+    // change points than that kernel handles (the flag is uniform)
+    if (a.dense && *as_global(a.dense) == 0) return;
     constexpr int kH = adj_halo(M);
     float2* G = reinterpret_cast<float2*>(smem4);
     const int nx = a.nx, LP = (nx + 1) / 2 + 2 * kH, r = blockIdx.x;
@@ -242,7 +252,11 @@ __global__ void __launch_bounds__(kAdjThreads) k_demigrate_reg(AdjArgs a)
         L.i0 = L.live0 ? a.image[(size_t)k * nx + L.c0] : 0.0;
         L.i1 = L.live1 ? a.image[(size_t)k * nx + L.c1] : 0.0;
     }
-    L.fl0 = L.fl1 = L.sv0 = L.sv1 = 0.0;
+    // the first refill (step nz-3, for step nz-4) compares with row nz-3,
+    // whose flag (against row nz-2) is never loaded: the first step moves
+    // this flagged placeholder into sp, which makes that refill unconditional
+    L.sn0 = L.sn1 = -0.0;
+    L.sp0 = L.sp1 = -0.0;
     __syncthreads();
 
     bool first = true;
@@ -268,6 +282,413 @@ int launch_reg(const AdjArgs& a, size_t lds, hipStream_t s)
     return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
 }
 
+
+// ---------------------------------------------------------------------------
+// Folded form.  Write j(y) for the table entry of point y (this frequency,
+// row k).  Where j is constant over x-M..x+M, E^H at x is the Eq. (1) FIR
+// with the conjugated taps of x itself, folded like the forward step.  In
+// general, telescoping h_j(y) - h_j(x) over the points between x and y gives
+//   (E^H q)[x] = sum_n conj(h_j(x)[|n|]) q[x+n]                 (own filter)
+//     + sum over change points c (j(c) != j(c-1)), with D_c = h_j(c) - h_j(c-1):
+//         x = c-d, d = 1..M:     + sum_{e=0..M-d}   conj(D_c[d+e])   q[c+e]
+//         x = c+d, d = 0..M-1:   - sum_{e=0..M-d-1} conj(D_c[d+1+e]) q[c-1-e]
+// so each change point adds a triangle of M(M+1) products to the 2M outputs
+// around it.  In layered media a row has a few change points (they sit where
+// an interface or a body crosses it), so the step costs about what the
+// forward step costs.  Change points are those of the slowness (a velocity
+// change that keeps the entry adds exact zeros).
+//
+// Mapping: as the forward register-tap kernel (two outputs per thread, two
+// alternating tap sets, plane ping-pong in LDS, one barrier per step).  A
+// wave owns 128 consecutive outputs and adds the corrections of its own
+// outputs: the triangle of a change point is cut into at most 64 chunks of
+// at most T terms (a fixed table, one chunk per lane), each lane sums its
+// chunk and adds it to the output in LDS after the owner's store, in the
+// same wave, so no extra barrier is needed; the chunks of one output are
+// added one rank after another, so the result is run-to-run identical.
+// The differences D_c of the next step are built during a step: the entry
+// pairs (from the change-point pre-pass) are loaded two steps ahead, the two
+// table rows one step ahead, and the differences go to an LDS cache before
+// the step's barrier.
+// ---------------------------------------------------------------------------
+constexpr int adj_chunk_count(int M, int T)
+{
+    int n = 0;
+    for (int d = 1; d <= M; ++d) n += (M - d + 1 + T - 1) / T;
+    for (int d = 0; d < M; ++d) n += (M - d + T - 1) / T;
+    return n;
+}
+
+constexpr int adj_chunk_len(int M)
+{
+    int T = 1;
+    while (adj_chunk_count(M, T) > 64) ++T;
+    return T;
+}
+
+// Chunk of the triangle that lane `lane` sums: side 0 = outputs left of the
+// change point (x = c-d), 1 = right (x = c+d); terms [e0, e0+len); rank =
+// position of the chunk among those of its output.  len = 0: no chunk.
+struct AdjChunk {
+    int side, d, e0, len, rank;
+};
+
+__device__ AdjChunk adj_lane_chunk(int lane, int M, int T)
+{
+    AdjChunk c = {0, 0, 0, 0, 0};
+    int idx = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int d0 = s == 0 ? 1 : 0, d1 = s == 0 ? M + 1 : M;
+        for (int d = d0; d < d1; ++d) {
+            const int t = s == 0 ? M - d + 1 : M - d;
+            for (int e = 0, q = 0; e < t; e += T, ++q, ++idx)
+                if (idx == lane) c = AdjChunk{s, d, e, t - e < T ? t - e : T, q};
+        }
+    }
+    return c;
+}
+
+// Two outputs x0, x0+1 of the folded FIR with conjugated taps,
+// sum_n conj(h[n]) (w[M-n] + w[M+n]), from the window w[i] = P[x0 - M + i]
+// (16-byte LDS reads); the conjugation is a sign in the multiply-adds.  Two
+// passes (taps 0..P, then P+1..M), each reading only the window part it uses,
+// with a scheduling barrier between them: the whole window would take 72
+// registers next to the two tap sets.
+template <int M, int LO, int HI>
+__device__ __forceinline__ void fold2_pass(const float4* __restrict__ w4, const float2 (&h0)[M + 1],
+                                           const float2 (&h1)[M + 1], float2& a0, float2& a1)
+{
+    // window indices this pass reads: out0 uses M-n, M+n; out1 M+1-n, M+1+n
+    constexpr int lo = M - HI, hi = M + 1 + HI;                 // outer bounds
+    constexpr int ilo = lo / 2, ihi = hi / 2;
+    float2 w[2 * M + 2];
+#pragma unroll
+    for (int i = ilo; i <= ihi; ++i) {
+        const bool inner_gap = LO > 0 && 2 * i > M - LO + 1 && 2 * i + 1 < M + LO;
+        if (inner_gap) continue;
+        // a native 4-float vector keeps the read one 16-byte LDS access (the
+        // HIP float4 struct is copied field by field, and 8-byte reads at a
+        // 16-byte lane stride conflict on the banks)
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        const v4f q = *reinterpret_cast<const v4f*>(w4 + i);
+        w[2 * i] = make_float2(q.x, q.y);
+        w[2 * i + 1] = make_float2(q.z, q.w);
+    }
+#pragma unroll
+    for (int n = LO; n <= HI; ++n) {
+        if (n == 0) {
+            a0.x = fmaf(h0[0].x, w[M].x, a0.x);
+            a0.x = fmaf(h0[0].y, w[M].y, a0.x);
+            a0.y = fmaf(h0[0].x, w[M].y, a0.y);
+            a0.y = fmaf(-h0[0].y, w[M].x, a0.y);
+            a1.x = fmaf(h1[0].x, w[M + 1].x, a1.x);
+            a1.x = fmaf(h1[0].y, w[M + 1].y, a1.x);
+            a1.y = fmaf(h1[0].x, w[M + 1].y, a1.y);
+            a1.y = fmaf(-h1[0].y, w[M + 1].x, a1.y);
+            continue;
+        }
+        const float2 s0 = make_float2(w[M - n].x + w[M + n].x, w[M - n].y + w[M + n].y);
+        const float2 s1 = make_float2(w[M + 1 - n].x + w[M + 1 + n].x, w[M + 1 - n].y + w[M + 1 + n].y);
+        a0.x = fmaf(h0[n].x, s0.x, a0.x);
+        a0.x = fmaf(h0[n].y, s0.y, a0.x);
+        a0.y = fmaf(h0[n].x, s0.y, a0.y);
+        a0.y = fmaf(-h0[n].y, s0.x, a0.y);
+        a1.x = fmaf(h1[n].x, s1.x, a1.x);
+        a1.x = fmaf(h1[n].y, s1.y, a1.x);
+        a1.y = fmaf(h1[n].x, s1.y, a1.y);
+        a1.y = fmaf(-h1[n].y, s1.x, a1.y);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void fold2(const float2* __restrict__ win, const float2 (&h0)[M + 1],
+                                      const float2 (&h1)[M + 1], float2& o0, float2& o1)
+{
+    constexpr int P = M / 2;
+    const float4* w4 = reinterpret_cast<const float4*>(win);
+    float2 a0 = make_float2(0.0f, 0.0f), a1 = a0;
+    fold2_pass<M, 0, P>(w4, h0, h1, a0, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    fold2_pass<M, P + 1, M>(w4, h0, h1, a0, a1);
+    o0 = a0;
+    o1 = a1;
+}
+
+// LDS of the folded kernel: two planes, then per parity the differences
+// D_c[1..M], the change count and the positions.
+__host__ __device__ constexpr int fold_plane_len(int tsub, int M) { return 2 * tsub + 2 * M + 2; }
+__host__ __device__ constexpr size_t fold_lds(int tsub, int M)
+{
+    return (size_t)2 * fold_plane_len(tsub, M) * sizeof(float2) +
+           (size_t)2 * kAdjKmax * M * sizeof(float2) + (size_t)2 * (kAdjKmax + 1) * sizeof(int);
+}
+
+// A lane's chunk, packed: side (bit 0), d (bits 1-6), e0 (7-12), len (13-18),
+// rank (19-21).
+__device__ __forceinline__ int pack_chunk(const AdjChunk& c)
+{
+    return c.side | (c.d << 1) | (c.e0 << 7) | (c.len << 13) | (c.rank << 19);
+}
+
+struct FoldState {
+    int t, x0, lane, xw, LB, chunk;
+    bool ok0, ok1;
+    int c0, c1;        // image columns (clamped into the section)
+    double ar;
+    // loader: thread t builds D_c[m] of change point i, t = i*M + m-1
+    bool on;
+    int jp;            // (left | right << 16) entries of change point i, next row
+    int pos, pos_cur;  // its position (next row, the row being built)
+    int cnt;           // change count of the next row (loaded a step ahead)
+    float2 hl, hr;     // table taps in flight
+};
+
+template <int M>
+__device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* dh, int* cc, int* cp,
+                                          FoldState& F, int k, float2 (&h)[2][M + 1], double2& sn,
+                                          double2& img)
+{
+    constexpr int T = adj_chunk_len(M);
+    constexpr int R = (M + T - 1) / T;
+    const int nx = a.nx;
+    const double2 cimg = img;
+    // change points of row k (cache k&1, complete since the last barrier)
+    // that reach this wave's outputs: read before the FIR so that their LDS
+    // latency overlaps it
+    const int n_cur = cc[k & 1];
+    const int mypos = F.lane < n_cur ? cp[(k & 1) * kAdjKmax + F.lane] : 0;
+    const bool rel = F.lane < n_cur && mypos >= F.xw - M + 1 && mypos <= F.xw + 127 + M;
+    // row k-1's change count, loaded a step ago (uniform)
+    const int cnt = __builtin_amdgcn_readfirstlane(F.cnt);
+    const int n_build = cnt < a.kmax ? cnt : a.kmax;
+    const int i_ld = F.t / M, m_ld = F.t - i_ld * M + 1;
+    const bool build = k >= 1 && F.on && i_ld < n_build;
+    // loader: table rows of row k-1's change points (entries loaded a step ago)
+    if (build) {
+        F.hr = load_global(a.tab + (size_t)((unsigned)F.jp >> 16) * (M + 1) + m_ld);
+        F.hl = load_global(a.tab + (size_t)((unsigned)F.jp & 0xffffu) * (M + 1) + m_ld);
+    }
+    F.pos_cur = F.pos;
+    // prefetches for the next steps, branch-free (rows clamped; values past
+    // the top are unused): slowness row k-1 (flagged where it differs from
+    // row k) for the refill at the end of this step, image row k-1, and the
+    // change points of row k-2 for the next step's loader
+    {
+        const int ks = k >= 1 ? k - 1 : 0, kn = k >= 2 ? k - 2 : 0;
+        sn = load_global(reinterpret_cast<const double2*>(a.slow + (size_t)ks * a.ldp + F.x0));
+        img = make_double2(a.image[(size_t)ks * nx + F.c0], a.image[(size_t)ks * nx + F.c1]);
+        F.cnt = *as_global(&a.chg[kn].cnt);
+        const int il = F.on ? i_ld : 0;
+        F.pos = *as_global(&a.chg[kn].pos[il]);
+        F.jp = *as_global(a.jpair + ((size_t)kn * a.nw + blockIdx.x) * kAdjKmax + il);
+    }
+    // own-filter FIR on Q_{k+1} (plane (k+1)&1), plus the image row
+    const int LB = F.LB;
+    const float2* Pin = sm + ((k + 1) & 1) * LB;
+    float2* Pout = sm + (k & 1) * LB + M;
+    float2 o0, o1;
+    fold2<M>(Pin + F.x0, h[0], h[1], o0, o1);
+    o0.x += (float)cimg.x;
+    o1.x += (float)cimg.y;
+    if (F.ok0) Pout[F.x0] = o0;
+    if (F.ok1) Pout[F.x0 + 1] = o1;
+    // corrections of this wave's outputs around the change points of row k:
+    // per change point every lane reads its chunk's T differences and window
+    // values at once (addresses clamped into the arrays, terms past the
+    // chunk multiplied by zero), then adds the sum after the owner's store
+    {
+        unsigned long long mask = __ballot(rel);
+        const float2* dk = dh + (k & 1) * kAdjKmax * M;
+        const int side = F.chunk & 1, d = (F.chunk >> 1) & 63, e0 = (F.chunk >> 7) & 63;
+        const int len = (F.chunk >> 13) & 63, rank = (F.chunk >> 19) & 7;
+        const int qs = side ? -1 : 1;
+        const int doff = (side ? d : d - 1) + e0;   // first difference index (m - 1)
+        while (mask) {
+            const int i = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int c = __builtin_amdgcn_readlane(mypos, i);
+            const int x = side ? c + d : c - d;
+            const bool act = len > 0 && x >= F.xw && x < F.xw + 128 && x >= 0 && x < nx;
+            const int q0 = M + (side ? c - 1 - e0 : c + e0);
+            // terms past the chunk read Pin[0], a zero of the plane's halo
+            float2 hd[T], qv[T];
+#pragma unroll
+            for (int e = 0; e < T; ++e) {
+                int di = doff + e;
+                di = di < 0 ? 0 : (di > M - 1 ? M - 1 : di);
+                const int qi = e < len ? q0 + e * qs : 0;
+                hd[e] = dk[i * M + di];
+                qv[e] = Pin[qi];
+            }
+            float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+            for (int e = 0; e < T; ++e) {
+                acc.x = fmaf(hd[e].x, qv[e].x, acc.x);
+                acc.x = fmaf(hd[e].y, qv[e].y, acc.x);
+                acc.y = fmaf(hd[e].x, qv[e].y, acc.y);
+                acc.y = fmaf(-hd[e].y, qv[e].x, acc.y);
+            }
+            if (side) acc = make_float2(-acc.x, -acc.y);
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (act && rank == q) {
+                    __hip_atomic_fetch_add(&Pout[x].x, acc.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(&Pout[x].y, acc.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+        }
+    }
+    if (k >= 1) {
+        // differences of row k-1 into the other cache (read from step k-1 on)
+        const int kp = (k - 1) & 1;
+        if (build) {
+            dh[(kp * kAdjKmax + i_ld) * M + m_ld - 1] = make_float2(F.hr.x - F.hl.x, F.hr.y - F.hl.y);
+            if (m_ld == 1) cp[kp * kAdjKmax + i_ld] = F.pos_cur;
+        }
+        if (F.t == 0) cc[kp] = n_build;
+        // taps of step k-1 where row k-1 differs from row k; the FIR of the
+        // next step waits for them (mostly L1 hits: the rows of one frequency)
+        if (slowness_changed(sn.x))
+            load_taps_adj<M>(h[0], a.tab + (size_t)index_of_slowness(F.ar, a.b, a.nk, slowness_value(sn.x)) * (M + 1));
+        if (slowness_changed(sn.y))
+            load_taps_adj<M>(h[1], a.tab + (size_t)index_of_slowness(F.ar, a.b, a.nk, slowness_value(sn.y)) * (M + 1));
+    }
+    __syncthreads();
+}
+
+template <int M>
+__global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
+{
+    if (*as_global(a.dense) != 0) return;  // uniform: the product kernel runs
+    extern __shared__ float4 smem4[];
+    constexpr int T = adj_chunk_len(M);
+    const int tsub = blockDim.x, nx = a.nx, nz = a.nz, r = blockIdx.x;
+    FoldState F;
+    F.LB = fold_plane_len(tsub, M);
+    float2* sm = reinterpret_cast<float2*>(smem4);
+    float2* dh = sm + 2 * F.LB;                                    // [2][kAdjKmax][M]
+    int* cc = reinterpret_cast<int*>(dh + 2 * kAdjKmax * M);       // [2]
+    int* cp = cc + 2;                                              // [2][kAdjKmax]
+    F.t = threadIdx.x;
+    F.x0 = 2 * F.t;
+    F.lane = F.t & 63;
+    F.xw = (F.t >> 6) * 128;
+    F.ok0 = F.x0 < nx;
+    F.ok1 = F.x0 + 1 < nx;
+    F.c0 = F.ok0 ? F.x0 : 0;
+    F.c1 = F.ok1 ? F.x0 + 1 : 0;
+    F.ar = a.omega[r] / a.dk;
+    F.chunk = pack_chunk(adj_lane_chunk(F.lane, M, T));
+    const int i_ld = F.t / M, m_ld = F.t - i_ld * M + 1;
+    F.on = i_ld < a.kmax;
+
+    for (int i = F.t; i < 2 * F.LB; i += tsub) sm[i] = make_float2(0.0f, 0.0f);
+    __syncthreads();
+    // Q_{nz-1} = image row nz-1, in plane (nz-1)&1
+    {
+        float2* P = sm + ((nz - 1) & 1) * F.LB + M;
+        if (F.ok0) P[F.x0] = make_float2((float)a.image[(size_t)(nz - 1) * nx + F.x0], 0.0f);
+        if (F.ok1) P[F.x0 + 1] = make_float2((float)a.image[(size_t)(nz - 1) * nx + F.x0 + 1], 0.0f);
+    }
+    // prologue: differences of the first step (row nz-2) into cache
+    // (nz-2)&1; entries of row nz-3 loaded for the first step's loader
+    int k = nz - 2;
+    {
+        const int c = a.chg[k].cnt;
+        const int n = c < a.kmax ? c : a.kmax;
+        if (F.on && i_ld < n) {
+            const int jp = a.jpair[((size_t)k * a.nw + r) * kAdjKmax + i_ld];
+            const float2 hr = a.tab[(size_t)((unsigned)jp >> 16) * (M + 1) + m_ld];
+            const float2 hl = a.tab[(size_t)((unsigned)jp & 0xffffu) * (M + 1) + m_ld];
+            dh[((k & 1) * kAdjKmax + i_ld) * M + m_ld - 1] = make_float2(hr.x - hl.x, hr.y - hl.y);
+            if (m_ld == 1) cp[(k & 1) * kAdjKmax + i_ld] = a.chg[k].pos[i_ld];
+        }
+        if (F.t == 0) cc[k & 1] = n;
+        const int kn = k >= 1 ? k - 1 : k;
+        F.cnt = a.chg[kn].cnt;
+        F.pos = F.on ? a.chg[kn].pos[i_ld] : 0;
+        F.jp = F.on ? a.jpair[((size_t)kn * a.nw + r) * kAdjKmax + i_ld] : 0;
+        F.pos_cur = 0;
+        F.hl = F.hr = make_float2(0.0f, 0.0f);
+    }
+    // taps of the first step (row nz-2)
+    float2 h[2][M + 1];
+    {
+        const double2 s0 = *reinterpret_cast<const double2*>(a.slow + (size_t)k * a.ldp + F.x0);
+        load_taps_adj<M>(h[0], a.tab + (size_t)index_of_slowness(F.ar, a.b, a.nk, slowness_value(s0.x)) * (M + 1));
+        load_taps_adj<M>(h[1], a.tab + (size_t)index_of_slowness(F.ar, a.b, a.nk, slowness_value(s0.y)) * (M + 1));
+    }
+    double2 sn = make_double2(0.0, 0.0);
+    double2 img = make_double2(a.image[(size_t)k * nx + F.c0], a.image[(size_t)k * nx + F.c1]);
+    __syncthreads();
+
+    for (; k >= 0; --k) fold_step<M>(a, sm, dh, cc, cp, F, k, h, sn, img);
+    const float2* P0 = sm + M;  // Q_0 is in plane 0
+    if (F.ok0) a.out[(size_t)F.x0 * a.nw + r] = P0[F.x0];
+    if (F.ok1) a.out[(size_t)(F.x0 + 1) * a.nw + r] = P0[F.x0 + 1];
+}
+
+template <int M>
+int launch_fold(const AdjArgs& a, hipStream_t s)
+{
+    const int tsub = ((a.nx + 1) / 2 + 63) / 64 * 64;
+    const size_t lds = fold_lds(tsub, M);
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_demigrate_fold<M>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return MIG_E_DEVICE;
+    hipLaunchKernelGGL(k_demigrate_fold<M>, dim3(a.nw), dim3(tsub), lds, s, a);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+// Change-point pre-pass, one workgroup per depth row: the first wave lists the
+// points where the slowness changes (ballot compaction, increasing x) and
+// flags the launch dense past kmax; then every thread forms (left, right)
+// table entries of the listed points for its frequencies, with the look-up
+// of the depth-stepping kernels.
+__global__ void __launch_bounds__(256) k_adj_changes(AdjArgs a)
+{
+    __shared__ double s_l[kAdjKmax], s_r[kAdjKmax];
+    __shared__ int s_n;
+    const int k = blockIdx.x;
+    const double* srow = a.slow + (size_t)k * a.ldp;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int count = 0;
+        for (int x0 = 1; x0 < a.nx; x0 += 64) {
+            const int x = x0 + lane;
+            double sl = 0.0, sr = 0.0;
+            bool chg = false;
+            if (x < a.nx) {
+                sl = slowness_value(srow[x - 1]);
+                sr = slowness_value(srow[x]);
+                chg = __double_as_longlong(sl) != __double_as_longlong(sr);
+            }
+            const unsigned long long m = __ballot(chg);
+            const int slot = count + __popcll(m & ((1ull << lane) - 1ull));
+            if (chg && slot < kAdjKmax) {
+                a.chg[k].pos[slot] = x;
+                s_l[slot] = sl;
+                s_r[slot] = sr;
+            }
+            count += __popcll(m);
+        }
+        if (lane == 0) {
+            a.chg[k].cnt = count;
+            s_n = count < a.kmax ? count : a.kmax;
+            if (count > a.kmax)
+                __hip_atomic_fetch_or(as_global(a.dense), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    const int n = s_n;
+    for (int e = threadIdx.x; e < a.nw * n; e += blockDim.x) {
+        const int r = e / n, i = e - r * n;
+        const double ar = a.omega[r] / a.dk;
+        a.jpair[((size_t)k * a.nw + r) * kAdjKmax + i] =
+            (int)((unsigned)index_of_slowness(ar, a.b, a.nk, s_l[i]) |
+                  ((unsigned)index_of_slowness(ar, a.b, a.nk, s_r[i]) << 16));
+    }
+}
 }  // namespace
 
 bool adjoint_uses_registers(int nx, int M, size_t lds_limit)
@@ -288,6 +709,39 @@ int launch_demigrate_reg(const AdjArgs& a, hipStream_t s)
     MIG_ADJ_CASE(10) MIG_ADJ_CASE(11) MIG_ADJ_CASE(12) MIG_ADJ_CASE(13) MIG_ADJ_CASE(14)
     MIG_ADJ_CASE(15) MIG_ADJ_CASE(16) MIG_ADJ_CASE(17)
 #undef MIG_ADJ_CASE
+    default: return MIG_E_ARG;
+    }
+}
+
+bool adjoint_uses_fold(int nx, int M)
+{
+    return nx <= 2 * kAdjThreads && M >= 1 && M <= kAdjMaxM && adjoint_fold_kmax(nx, M) >= 1;
+}
+
+int adjoint_fold_kmax(int nx, int M)
+{
+    // one loader thread per (change point, tap 1..M)
+    const int tsub = ((nx + 1) / 2 + 63) / 64 * 64;
+    const int k = M >= 1 ? tsub / M : 0;
+    return k < kAdjKmax ? k : kAdjKmax;
+}
+
+int launch_adj_changes(const AdjArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_changes, dim3(a.nz - 1), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? MIG_OK : MIG_E_DEVICE;
+}
+
+int launch_demigrate_fold(const AdjArgs& a, hipStream_t s)
+{
+    switch (a.M) {
+#define MIG_FOLD_CASE(m) \
+    case m: return launch_fold<m>(a, s);
+    MIG_FOLD_CASE(1) MIG_FOLD_CASE(2) MIG_FOLD_CASE(3) MIG_FOLD_CASE(4)
+    MIG_FOLD_CASE(5) MIG_FOLD_CASE(6) MIG_FOLD_CASE(7) MIG_FOLD_CASE(8) MIG_FOLD_CASE(9)
+    MIG_FOLD_CASE(10) MIG_FOLD_CASE(11) MIG_FOLD_CASE(12) MIG_FOLD_CASE(13) MIG_FOLD_CASE(14)
+    MIG_FOLD_CASE(15) MIG_FOLD_CASE(16) MIG_FOLD_CASE(17)
+#undef MIG_FOLD_CASE
     default: return MIG_E_ARG;
     }
 }

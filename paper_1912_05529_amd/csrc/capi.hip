@@ -702,11 +702,21 @@ MIG_API int mig_migrate_batched(const mig_section* secs, int32_t nsec, const mig
                      as_stream(stream));
 }
 
-MIG_API size_t mig_demigrate_workspace_size(int32_t nx, int32_t nz, const mig_table_desc* d)
+// Demigration workspace: [slowness rows][dense flag][change points per row]
+// [(left, right) entries per row, frequency and change point].
+static size_t demig_slow_bytes(int32_t nx, int32_t nz)
 {
-    if (!desc_valid(d) || nx < 1 || nx > MIG_MAX_NX || nz < 1) return 0;
-    size_t rows = nz > 1 ? (size_t)(nz - 1) : 1;
+    const size_t rows = nz > 1 ? (size_t)(nz - 1) : 1;
     return align_up(rows * row_stride(nx) * sizeof(double), kAlign);
+}
+
+MIG_API size_t mig_demigrate_workspace_size(int32_t nx, int32_t nz, int32_t nw,
+                                            const mig_table_desc* d)
+{
+    if (!desc_valid(d) || !sizes_ok(nx, nw) || nz < 1) return 0;
+    const size_t rows = nz > 1 ? (size_t)(nz - 1) : 1;
+    return demig_slow_bytes(nx, nz) + kAlign + align_up(rows * sizeof(AdjRow), kAlign) +
+           align_up(rows * nw * kAdjKmax * sizeof(int), kAlign);
 }
 
 MIG_API int mig_demigrate(const double* image, const float* vel, const double* omega,
@@ -716,7 +726,7 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
     if (!desc_valid(d) || !image || !vel || !omega || !tab32 || !data || !sizes_ok(nx, nw) ||
         nz < 1)
         return MIG_E_ARG;
-    const size_t need = mig_demigrate_workspace_size(nx, nz, d);
+    const size_t need = mig_demigrate_workspace_size(nx, nz, nw, d);
     if (!ws || ws_bytes < need) return MIG_E_WORKSPACE;
     if (overlap(ws, ws_bytes, data, (size_t)nx * nw * sizeof(mig_c64))) return MIG_E_ARG;
     int dev = 0, lds_max = 65536;
@@ -726,11 +736,22 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
     const int M = (d->ntaps - 1) / 2;
     AdjArgs a = {};
     const bool reg = adjoint_uses_registers(nx, M, (size_t)lds_max);
+    const bool fold = reg && nz > 1 && d->nk <= 65536 && adjoint_uses_fold(nx, M);
     a.chunk = adjoint_chunk(nx, M, (size_t)lds_max);
     if (!reg && a.chunk < 1) return MIG_E_ARG;
     hipStream_t s = as_stream(stream);
+    char* base = static_cast<char*>(ws);
+    const size_t rows = nz > 1 ? (size_t)(nz - 1) : 1;
     a.image = image;
-    a.slow = static_cast<const double*>(ws);
+    a.slow = reinterpret_cast<const double*>(base);
+    base += demig_slow_bytes(nx, nz);
+    int* dense = reinterpret_cast<int*>(base);
+    base += kAlign;
+    a.chg = reinterpret_cast<AdjRow*>(base);
+    base += align_up(rows * sizeof(AdjRow), kAlign);
+    a.jpair = reinterpret_cast<int*>(base);
+    a.dense = fold ? dense : nullptr;
+    a.kmax = fold ? adjoint_fold_kmax(nx, M) : 0;
     a.omega = omega;
     a.tab = reinterpret_cast<const float2*>(tab32);
     a.out = reinterpret_cast<float2*>(data);
@@ -750,13 +771,25 @@ MIG_API int mig_demigrate(const double* image, const float* vel, const double* o
         sa.one.nx = nx;
         sa.one.nsteps = nz - 1;
         sa.one.ldp = a.ldp;
-        // change flags two rows apart: walking depth upward with two tap sets
-        // that alternate between steps, the register-tap kernel refills a
-        // point's taps where its row differs from the row two steps below
-        int rc = launch_slowness(sa, nz - 1, a.ldp, 2, s);
+        // the slowness launch zeroes the dense flag
+        sa.status = dense;
+        sa.reset_status = 1;
+        // change flags against the row one step deeper: walking depth upward,
+        // the register-tap kernels refill a point's taps where its row differs
+        // from the row below (the product kernel, whose two alternating tap
+        // sets are two rows apart, where either of two rows in a row differs)
+        int rc = launch_slowness(sa, nz - 1, a.ldp, -1, s);
         if (rc != MIG_OK) return rc;
     }
-    return reg ? launch_demigrate_reg(a, s) : launch_demigrate(a, s);
+    if (!reg) return launch_demigrate(a, s);
+    if (fold) {
+        // the folded kernel runs unless some row has more change points than
+        // it handles; the product kernel, launched after it, runs only then
+        int rc = launch_adj_changes(a, s);
+        if (rc == MIG_OK) rc = launch_demigrate_fold(a, s);
+        if (rc != MIG_OK) return rc;
+    }
+    return launch_demigrate_reg(a, s);
 }
 
 MIG_API size_t mig_transform_workspace_size(int32_t nt, int32_t nw)

@@ -79,6 +79,15 @@ struct BatchArgs {
     double b;              // kmin / dk
 };
 
+// Lateral change points of one depth row (x where the slowness differs from
+// x-1), as the folded adjoint kernel reads them: at most kAdjKmax per row.
+constexpr int kAdjKmax = 16;
+struct AdjRow {
+    int cnt;               // change points in the row (may exceed kAdjKmax)
+    int pos[kAdjKmax];     // the first min(cnt, kAdjKmax), increasing
+    int pad[3];
+};
+
 // Arguments of the demigration (adjoint) launch: one workgroup per frequency.
 struct AdjArgs {
     const double* image;   // [nz][nx] image rows (input)
@@ -86,6 +95,15 @@ struct AdjArgs {
     const double* omega;   // [nw]
     const float2* tab;     // [nk][M+1]
     float2* out;           // [nx][nw] surface plane (output)
+    // folded kernel: change points per row, their table entries per
+    // frequency [nz-1][nw][kAdjKmax] (left | right << 16; nk <= 65536), and
+    // the flag set when some row has more than kmax change points (then the
+    // product kernel runs instead); dense == nullptr: only the product (or
+    // general) kernel is launched
+    AdjRow* chg;
+    int* jpair;
+    int* dense;
+    int kmax;
     int nx, nz, nw, ldp, nk, M;
     int chunk;             // filter taps handled per LDS pass
     double dk, b;
@@ -181,7 +199,8 @@ int launch_index(const float* vel, const double* omega, int nx, int nw,
                  int nrows, int nk, double dk, double b, int32_t* idx,
                  hipStream_t s);
 // Slowness rows of every section of the launch (one launch for all), with the
-// change flag taken against the row `dist` steps earlier (0 = no flags).
+// change flag taken against the row `dist` steps earlier (negative: -dist
+// steps later; 0 = no flags).
 int launch_slowness(const BatchArgs& a, int max_rows, int max_ldp, int dist, hipStream_t s);
 // Row distance of the change flag a kernel variant reads.
 inline int flag_distance(int kind) { return kind == 1 ? 2 : (kind == 0 ? 0 : 1); }
@@ -195,6 +214,13 @@ int launch_demigrate(const AdjArgs& a, hipStream_t s);
 // Register-tap adjoint kernel: usable for these sizes within an LDS budget?
 bool adjoint_uses_registers(int nx, int M, size_t lds_limit);
 int launch_demigrate_reg(const AdjArgs& a, hipStream_t s);
+// Folded adjoint kernel (own-filter FIR + corrections at lateral change
+// points): usable for these sizes?  Change points it handles per row.
+bool adjoint_uses_fold(int nx, int M);
+int adjoint_fold_kmax(int nx, int M);
+// Change-point pre-pass (after the slowness rows), then the folded kernel.
+int launch_adj_changes(const AdjArgs& a, hipStream_t s);
+int launch_demigrate_fold(const AdjArgs& a, hipStream_t s);
 // Transform along t: builds the FP32 DFT matrix B [nt][2 nw] and computes the
 // plane out [nx][nw] = section [nx][nt] . B on the matrix cores.
 int launch_transform(const float* section, int nx, int nt, double dt, const double* omega,

@@ -171,7 +171,8 @@ __device__ __forceinline__ void group_shape(const SecDev& S, int kind, int& G, i
 }
 
 // slow[k][x] = slowness_of(vel[k][min(x, nx-1)]) for x < ldp, every section,
-// with the sign bit set where it differs (bitwise) from row k - dist; also
+// with the sign bit set where it differs (bitwise) from row k - dist (when
+// that row exists); also
 // zeroes each section's block counters (one launch fewer before the depth
 // stepping).
 __global__ void k_slowness(BatchArgs a, int dist)
@@ -197,8 +198,12 @@ __global__ void k_slowness(BatchArgs a, int dist)
         const int xc = x < S.nx ? x : S.nx - 1;
         double v = slowness_of(S.vel[k * S.nx + xc]);
         long long bits = __double_as_longlong(v);
-        if (dist > 0 && (int)k >= dist) {
-            long long prev = __double_as_longlong(slowness_of(S.vel[(k - dist) * S.nx + xc]));
+        // dist > 0: flag against the row dist steps earlier (depth stepping
+        // downward); dist < 0: against the row -dist steps later (the adjoint
+        // walks upward)
+        const long long kr = (long long)k - dist;
+        if (dist != 0 && kr >= 0 && kr < S.nsteps) {
+            long long prev = __double_as_longlong(slowness_of(S.vel[(size_t)kr * S.nx + xc]));
             if (bits != prev) bits |= (long long)kSignBit;
         }
         slow[e] = __longlong_as_double(bits);

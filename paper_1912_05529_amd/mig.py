@@ -97,7 +97,7 @@ def lib():
         "mig_kernel_kind": ([i32, i32], C.c_int),
         "mig_transform_workspace_size": ([i32, i32], sz),
         "mig_transform_t": ([P, i32, i32, C.c_double, P, i32, P, P, sz, P], C.c_int),
-        "mig_demigrate_workspace_size": ([i32, i32, D], sz),
+        "mig_demigrate_workspace_size": ([i32, i32, i32, D], sz),
         "mig_demigrate": ([P, P, P, P, D, i32, i32, i32, P, P, sz, P], C.c_int),
         "mig_batch_workspace_size": ([C.POINTER(CSection), i32, D, C.POINTER(CTuning)], sz),
         "mig_migrate_batched": ([C.POINTER(CSection), i32, P, D, C.POINTER(CTuning), P, sz, P],
@@ -354,9 +354,9 @@ def migrate_batched(batch, tab32, desc, tune=None, ws=None):
     return [b["image"] for b in batch]
 
 
-def demigrate_workspace_size(nx, nz, desc) -> int:
+def demigrate_workspace_size(nx, nz, nw, desc) -> int:
     cd = cdesc(desc)
-    return int(lib().mig_demigrate_workspace_size(nx, nz, C.byref(cd)))
+    return int(lib().mig_demigrate_workspace_size(nx, nz, nw, C.byref(cd)))
 
 
 def demigrate(image, vel, omega, tab32, desc, nw=None, out=None, ws=None):
@@ -371,7 +371,7 @@ def demigrate(image, vel, omega, tab32, desc, nw=None, out=None, ws=None):
         out = torch.empty((nx, nw), dtype=torch.complex64, device=image.device)
     _need(out, torch.complex64, (nx, nw), "data")
     if ws is None:
-        ws = torch.empty(max(demigrate_workspace_size(nx, nz, desc), 1), dtype=torch.uint8,
+        ws = torch.empty(max(demigrate_workspace_size(nx, nz, nw, desc), 1), dtype=torch.uint8,
                          device=image.device)
     cd = cdesc(desc)
     rc = lib().mig_demigrate(_p(image), _p(vel), _p(omega), _p(tab32), C.byref(cd), nx, nz, nw,

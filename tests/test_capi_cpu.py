@@ -128,6 +128,13 @@ def test_workspace_sizes_and_kernel_kinds(L):
     assert mig.kernel_kind(2049, 25) == 0
     assert mig.kernel_kind(512, 37) == 0
     assert mig.kernel_kind(512, 36) == -1
+    # demigration: slowness rows, the dense flag, per-row change points (80 bytes
+    # each) and (left, right) entries per row, frequency and change point (16)
+    al = lambda n: (n + 255) // 256 * 256
+    assert mig.demigrate_workspace_size(1024, 512, 200, d) == (
+        al(511 * 1024 * 8) + 256 + al(511 * 80) + al(511 * 200 * 16 * 4))
+    assert mig.demigrate_workspace_size(1024, 0, 200, d) == 0
+    assert mig.demigrate_workspace_size(1024, 4, 0, d) == 0
     # transform along t: the FP32 DFT matrix [nt][2 nw], nt <= 2^22
     assert mig.transform_workspace_size(1024, 200) == 1024 * 400 * 4
     assert mig.transform_workspace_size(4194304, 1) == 4194304 * 2 * 4

@@ -36,6 +36,7 @@ def test_demigrate_matches_oracle_adjoint(small):
     err = rel_l2(got, ref)
     print("demigrate vs FP64 oracle rel L2 %.3e" % err)
     assert err <= 1e-5
+    assert_rows_close(got, ref, 2e-5, "demigrate 64x64", axis=1)
 
 
 @pytest.mark.parametrize("nx,nz,nw,ntaps,layered", [
@@ -59,12 +60,89 @@ def test_demigrate_shapes_match_oracle(nx, nz, nw, ntaps, layered):
     err = rel_l2(got, ref)
     print("  rel L2 %.3e" % err)
     assert err <= 1e-5
+    assert_rows_close(got, ref, 2e-5, "demigrate nx=%d nz=%d" % (nx, nz), axis=1)
 
 
-@pytest.mark.parametrize("nx,nz,nw,ntaps", [(64, 64, 16, 35), (1024, 40, 12, 35),
-                                            (300, 33, 7, 25), (2100, 5, 3, 35), (1, 4, 2, 35)])
-def test_dot_product(nx, nz, nw, ntaps):
-    sec = synth.random_case(900 + nx, nx, nz, nw, ntaps=ntaps, nk=256, layered=False)
+def _dense_flag(ws, nx, nz):
+    """The flag the change-point pre-pass leaves in the demigration workspace
+    (right after the slowness rows, [nz-1][ldp] doubles, 256-byte aligned): 1
+    when some row has more lateral change points than the folded kernel
+    handles, so the product kernel ran instead."""
+    ldp = (nx + 255) // 256 * 256
+    off = ((nz - 1) * ldp * 8 + 255) // 256 * 256
+    return int(ws[off:off + 4].view(torch.int32).item())
+
+
+def _strips_case(seed, nx, nz, nw, ntaps, cuts, nan_strip=False, shift_every=0):
+    """Velocity in vertical strips with lateral changes at exactly `cuts`
+    (shifted right by one point every `shift_every` rows, so the lists change
+    from row to row), optionally one strip of NaN (entry 0); random data."""
+    sec = synth.random_case(seed, nx, nz, nw, ntaps=ntaps, nk=256)
+    rng = np.random.default_rng(seed)
+    speeds = rng.uniform(760.0, 2390.0, len(cuts) + 1)
+    if nan_strip:
+        speeds[len(speeds) // 2] = np.nan
+    v = np.empty((nz, nx), np.float32)
+    for k in range(nz):
+        sh = k // shift_every if shift_every else 0
+        edges = [0] + [min(c + sh, nx - 1) for c in sorted(cuts)] + [nx]
+        for i, (a, b) in enumerate(zip(edges[:-1], edges[1:])):
+            v[k, a:b] = speeds[i]
+    sec.vel = v
+    return sec
+
+
+WAVE_EDGES = [127, 128, 129, 255, 256, 384, 511, 512, 640, 767, 768, 896, 1000, 1023]
+
+
+@pytest.mark.parametrize("nx,nz,nw,ntaps,cuts,nan_strip,shift,dense", [
+    # change points on and next to wave boundaries (128-point waves), N = 35
+    (1024, 24, 5, 35, WAVE_EDGES, False, 3, 0),
+    # exactly as many change points per row as the folded kernel takes (16) ...
+    (1024, 9, 3, 35, list(range(40, 1024, 62))[:16], False, 0, 0),
+    # ... and one more in every row: the product kernel runs
+    (1024, 9, 3, 35, list(range(40, 1024, 60))[:17], False, 0, 1),
+    # ragged width, 25 taps, a NaN strip (entry 0)
+    (1000, 17, 4, 25, [1, 2, 3, 300, 301, 640, 998, 999], True, 4, 0),
+    # narrow sections: 129 points (two waves, 7 change points per row at most
+    # with 17 taps), 64 points (3), 3 taps
+    (129, 12, 4, 35, [1, 17, 63, 64, 65, 100, 128], False, 0, 0),
+    (129, 12, 4, 35, [1, 17, 63, 64, 65, 100, 127, 128], False, 0, 1),
+    (64, 10, 3, 35, [5, 31, 32], False, 2, 0),
+    (300, 15, 3, 3, [1, 2, 150, 151, 298, 299], False, 5, 0),
+])
+def test_demigrate_kernels_at_lateral_changes(nx, nz, nw, ntaps, cuts, nan_strip, shift, dense):
+    """Folded adjoint kernel (own-filter FIR plus corrections at lateral
+    change points) and its fallback, element by element against the FP64
+    oracle adjoint, with change points placed on wave boundaries, at the ends
+    of the section, at the per-row limit and one past it."""
+    sec = _strips_case(4100 + nx + len(cuts), nx, nz, nw, ntaps, cuts, nan_strip, shift)
+    print("strips nx=%d nz=%d nw=%d N=%d cuts=%d expect dense=%d" % (nx, nz, nw, ntaps, len(cuts),
+                                                                      dense), flush=True)
+    tab = mig.design_table(sec.desc, dev())
+    t = upload(sec)
+    rng = np.random.default_rng(nx + 3 * nz)
+    img = rng.standard_normal((nz, nx))
+    ws = torch.zeros(mig.demigrate_workspace_size(nx, nz, nw, sec.desc), dtype=torch.uint8,
+                     device=dev())
+    got = mig.demigrate(torch.from_numpy(img).to(dev()), t["vel"], t["omega"], tab["tab32"],
+                        sec.desc, ws=ws).cpu().numpy()
+    assert _dense_flag(ws, nx, nz) == dense
+    ot = oracle.design_table(sec.desc)[0]
+    ref = oracle.demigrate(sec.desc, ot, sec.omega, sec.vel, img)
+    assert_rows_close(got, ref, 2e-5, "strips demigrate nx=%d" % nx, axis=1)
+    # run-to-run identical (fixed order of the correction adds)
+    again = mig.demigrate(torch.from_numpy(img).to(dev()), t["vel"], t["omega"], tab["tab32"],
+                          sec.desc, ws=ws).cpu().numpy()
+    assert np.array_equal(got, again)
+
+
+@pytest.mark.parametrize("nx,nz,nw,ntaps,layered", [
+    (64, 64, 16, 35, False), (1024, 40, 12, 35, False), (300, 33, 7, 25, False),
+    (2100, 5, 3, 35, False), (1, 4, 2, 35, False),
+    (1024, 40, 12, 35, True), (517, 30, 6, 25, True)])
+def test_dot_product(nx, nz, nw, ntaps, layered):
+    sec = synth.random_case(900 + nx, nx, nz, nw, ntaps=ntaps, nk=256, layered=layered)
     tab = mig.design_table(sec.desc, dev())
     t = upload(sec)
     rng = np.random.default_rng(nx)
