@@ -440,16 +440,20 @@ struct FoldState {
     int jp;            // (left | right << 16) entries of change point i, next row
     int pos, pos_cur;  // its position (next row, the row being built)
     int cnt;           // change count of the next row (loaded a step ahead)
+    int i_ld, m_ld;    // loader role: change point i_ld, tap m_ld
     float2 hl, hr;     // table taps in flight
 };
 
 template <int M>
 __device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* dh, int* cc, int* cp,
-                                          FoldState& F, int k, float2 (&h)[2][M + 1], double2& sn,
-                                          double2& img)
+                                          FoldState& F, int k_in, float2 (&h)[2][M + 1],
+                                          double2& sn, double2& img)
 {
     constexpr int T = adj_chunk_len(M);
     constexpr int R = (M + T - 1) / T;
+    // the depth index is wave-uniform: keeping it scalar keeps every row
+    // address computation on the scalar unit
+    const int k = __builtin_amdgcn_readfirstlane(k_in);
     const int nx = a.nx;
     const double2 cimg = img;
     // change points of row k (cache k&1, complete since the last barrier)
@@ -461,7 +465,7 @@ __device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* 
     // row k-1's change count, loaded a step ago (uniform)
     const int cnt = __builtin_amdgcn_readfirstlane(F.cnt);
     const int n_build = cnt < a.kmax ? cnt : a.kmax;
-    const int i_ld = F.t / M, m_ld = F.t - i_ld * M + 1;
+    const int i_ld = F.i_ld, m_ld = F.m_ld;
     const bool build = k >= 1 && F.on && i_ld < n_build;
     // loader: table rows of row k-1's change points (entries loaded a step ago)
     if (build) {
@@ -477,7 +481,11 @@ __device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* 
         const int ks = k >= 1 ? k - 1 : 0, kn = k >= 2 ? k - 2 : 0;
         sn = load_global(reinterpret_cast<const double2*>(a.slow + (size_t)ks * a.ldp + F.x0));
         img = make_double2(a.image[(size_t)ks * nx + F.c0], a.image[(size_t)ks * nx + F.c1]);
-        F.cnt = *as_global(&a.chg[kn].cnt);
+        // a vector load: as a scalar load its completion would be tracked by
+        // the counter the FIR's LDS waits use, and they would wait for it
+        int zero = 0;
+        asm volatile("" : "+v"(zero));
+        F.cnt = *as_global(&a.chg[kn].cnt + zero);
         const int il = F.on ? i_ld : 0;
         F.pos = *as_global(&a.chg[kn].pos[il]);
         F.jp = *as_global(a.jpair + ((size_t)kn * a.nw + blockIdx.x) * kAdjKmax + il);
@@ -579,6 +587,8 @@ __global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
     F.ar = a.omega[r] / a.dk;
     F.chunk = pack_chunk(adj_lane_chunk(F.lane, M, T));
     const int i_ld = F.t / M, m_ld = F.t - i_ld * M + 1;
+    F.i_ld = i_ld;
+    F.m_ld = m_ld;
     F.on = i_ld < a.kmax;
 
     for (int i = F.t; i < 2 * F.LB; i += tsub) sm[i] = make_float2(0.0f, 0.0f);
