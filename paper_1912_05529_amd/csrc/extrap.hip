@@ -225,6 +225,18 @@ __device__ __forceinline__ void publish_block(const BatchArgs& a, const SecDev& 
     }
 }
 
+// Block b (steps 32b .. 32b+31) is published at the end of step 32b+33: its
+// last partial row was stored at the start of step 32b+32, the wait for all
+// memory operations at the start of step 32b+33 covers it, and the barrier
+// ending that step means every wave of the workgroup has passed that wait.
+// So no extra wait stands in the loop.  Blocks whose publishing step lies
+// past the last step are published after the loop.
+__device__ __forceinline__ bool publishes_at(int k) { return k >= kPublish + 1 && k % kPublish == 1; }
+__device__ __forceinline__ int published_in_loop(int nsteps)
+{
+    return nsteps - 1 >= kPublish + 1 ? (nsteps - 1 - (kPublish + 1)) / kPublish + 1 : 0;
+}
+
 __device__ __forceinline__ int load_relaxed(int* p)
 {
     return __hip_atomic_load(as_global(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -369,10 +381,8 @@ __device__ __forceinline__ void step_fast(const BatchArgs& a, const SecDev& S, f
     if (L.ok0) dst[0] = o0;
     if (L.ok1) dst[1] = o1;
     sn = p;
-    if (ROWS && k >= 1 && k % kPublish == 0) wait_vmem_all();
     __syncthreads();
-    // the partial row of step k-1 is now stored by every thread
-    if (ROWS && k >= 1 && k % kPublish == 0) publish_block(a, S, (k - 1) / kPublish);
+    if (ROWS && publishes_at(k)) publish_block(a, S, k / kPublish - 1);
 }
 
 // Register-tap kernel, two outputs per thread.  Sub-group of tsub threads per
@@ -436,7 +446,7 @@ __global__ void __launch_bounds__(512) k_extrap_fast(BatchArgs a)
         store_partial2(pr, o0.x, o1.x);
         wait_vmem_all();
         __syncthreads();
-        publish_block(a, S, (S.nsteps - 1) / kPublish);
+        for (int b = published_in_loop(S.nsteps); b * kPublish < S.nsteps; ++b) publish_block(a, S, b);
     }
     if (S.wout) {
         if (L.ok0) S.wout[(size_t)L.x0 * S.nw + L.r] = o0;
@@ -555,16 +565,15 @@ __global__ void __launch_bounds__(512) k_extrap_wide(BatchArgs a)
                     load_taps<M>(h[q], a.tab + (size_t)index_of_slowness(ar, a.b, a.nk,
                                                                          slowness_value(sn[q])) * (M + 1));
         }
-        if (ROWS && k >= 1 && k % kPublish == 0) wait_vmem_all();
         __syncthreads();
-        if (ROWS && k >= 1 && k % kPublish == 0) publish_block(a, S, (k - 1) / kPublish);
+        if (ROWS && publishes_at(k)) publish_block(a, S, k / kPublish - 1);
     }
     if (ROWS) {
         float* pr = live ? S.part + ((size_t)(S.nsteps - 1) * S.nw + r) * S.ldp + x0 : a.trash + x0;
         store_partial_q<Q>(pr, o, ok);
         wait_vmem_all();
         __syncthreads();
-        publish_block(a, S, (S.nsteps - 1) / kPublish);
+        for (int b = published_in_loop(S.nsteps); b * kPublish < S.nsteps; ++b) publish_block(a, S, b);
     }
     if (S.wout) {
 #pragma unroll
