@@ -45,6 +45,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (packed FMA, 256 CU, 2.4 GHz)
+# Without packed FP32 the VALU issues 64 FP32 lane-ops per clock per CU (78.6
+# TFLOP/s of FMA); the folded Eq. (1) step takes 4(M+1)+2M instructions for
+# 8(M+1)+2M FLOP (178 in 106 at 35 taps), so 178/106 x 39.3 T lane-op/s = 66
+# TFLOP/s is this instruction mix's ceiling, and 200 frequencies on 256 CUs
+# (one per workgroup) leave 200/256 of it: 51.6 TFLOP/s.
+CEIL_MIX_TFLOPS = 66.0
+CEIL_MIX_200CU_TFLOPS = 51.6
 METRIC = "f-x extrapolation G complex tap-MAC/s + image err vs FP64; batched/adjoint vs plain"
 
 
@@ -66,6 +73,10 @@ def parse():
                          "prints timings only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--batched-tune", default="4,32,3",
+                    help="omegas_per_group,reducers,outputs_mid for --profile batched (no "
+                         "autotuning inside a profiled run)")
+    ap.add_argument("--oracle-one-core", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -115,6 +126,90 @@ def timed(torch, fn, reps, warmup=1):
         for _ in range(reps):
             fn()
     return t.ms / reps
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_one_core():
+    """The oracle on one host core: the headline workload's first 40 of 200
+    frequencies (all 511 depth steps), in a child process with
+    OMP_NUM_THREADS=1 that touches no GPU; scaled to the whole workload it
+    is the one-core throughput (frequencies are independent)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-core"],
+                             env=env, capture_output=True, text=True, timeout=600, check=True)
+        return json.loads(out.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError, OSError) as e:
+        print("one-core oracle run failed: %s" % e, file=sys.stderr, flush=True)
+        return None
+
+
+def oracle_one_core_child():
+    import oracle
+    from paper_1912_05529_amd import synth
+    sec = synth.config2()
+    nsub = 40
+    otab = oracle.design_table(sec.desc)[0]
+    d64 = sec.data[:, :nsub].astype(np.complex64).astype(np.complex128)
+    t0 = time.time()
+    oracle.migrate(sec.desc, otab, sec.omega[:nsub].copy(), sec.vel, np.ascontiguousarray(d64))
+    t = time.time() - t0
+    macs = sec.nx * nsub * (sec.nz - 1) * sec.desc.ntaps
+    print(json.dumps({"cores": oracle.num_threads(), "frequencies_run": nsub,
+                      "seconds_run": round(t, 3), "seconds": round(t * sec.nw / nsub, 3),
+                      "value": round(macs / t / 1e9, 4), "unit": "G complex tap-MAC/s"}))
+
+
+def config1_line(torch, mig, synth, dev, args):
+    """Configuration 1 (128 x 128, 64 frequencies, 25 taps): small enough that
+    the step is latency, reported beside the headline."""
+    sec = synth.config1()
+    desc = sec.desc
+    N = desc.ntaps
+    M = (N - 1) // 2
+    tab = mig.design_table(desc, dev)
+    data = torch.from_numpy(sec.data.astype(np.complex64)).to(dev)
+    vel = torch.from_numpy(sec.vel).to(dev)
+    omega = torch.from_numpy(sec.omega).to(dev)
+    ws = torch.empty(mig.workspace_size(sec.nx, sec.nz - 1, sec.nw, desc), dtype=torch.uint8,
+                     device=dev)
+    img = torch.empty((sec.nz, sec.nx), dtype=torch.float64, device=dev)
+    reps = max(20, args.steps)
+    ms = timed(torch, lambda: mig.migrate(data, vel, omega, tab["tab32"], desc, ws=ws, out=img),
+               reps, warmup=max(3, args.warmup))
+    outputs = sec.nx * sec.nw * (sec.nz - 1)
+    tflops = outputs * (8 * (M + 1) + 2 * M) / (ms * 1e-3) / 1e12
+    out = {
+        "workload": "2-D constant velocity 2000 m/s (1000 m/s propagation), one diffraction "
+                    "hyperbola: nx=128, nz=128, 64 frequencies 5-40 Hz, 25-tap extrapolators, "
+                    "512-entry table, seed 1",
+        "ms_per_migration": round(ms, 4),
+        "G_tap_mac_per_s": round(outputs * N / (ms * 1e-3) / 1e9, 2),
+        "tflops_algorithmic": round(tflops, 3),
+        "frac_of_peak": round(tflops / PEAK_FP32_TFLOPS, 5),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        otab = oracle.design_table(desc)[0]
+        ref = oracle.migrate(desc, otab, sec.omega, sec.vel,
+                             sec.data.astype(np.complex64).astype(np.complex128))
+        got = img.cpu().numpy()
+        out["image_rel_l2_vs_fp64"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["table_rel_err_vs_fp64"] = float(np.abs(tab["tab64"].cpu().numpy() - otab).max() /
+                                             np.abs(otab).max())
+    print("config1: %.4f ms per migration" % ms, file=sys.stderr, flush=True)
+    return out
 
 
 # --------------------------------------------------------------------------- #
@@ -230,6 +325,11 @@ def headline(torch, mig, synth, dev, args):
             "traffic": traffic,
             "ms_per_launch": round(ms_kernel, 4),
             "flop_per_launch": flop_alg,
+            "frac_of_mix_ceiling": round(achieved / CEIL_MIX_TFLOPS, 4),
+            "frac_of_mix_ceiling_200_of_256_cus": round(achieved / CEIL_MIX_200CU_TFLOPS, 4),
+            "mix_ceiling_note": "66 TFLOP/s = unpacked FP32 issue with 178 FLOP per 106 "
+                                "instructions per output; 51.6 = the same with 200 of 256 CUs "
+                                "busy (one frequency per workgroup)",
         },
     }
     if not args.no_cpu_baseline:
@@ -248,6 +348,10 @@ def headline(torch, mig, synth, dev, args):
         t_mig = sorted(times)[1]
         gimg = img.cpu().numpy()
         res["image_rel_l2_vs_fp64"] = float(np.linalg.norm(gimg - ref) / np.linalg.norm(ref))
+        res["image_worst_elem_err_vs_fp64"] = float(np.abs(gimg - ref).max() / np.abs(ref).max())
+        t64 = tab["tab64"].cpu().numpy()
+        res["table_rel_err_vs_fp64"] = float(np.abs(t64 - otab).max() / np.abs(otab).max())
+        one = oracle_one_core()
         res["cpu_baseline"] = {
             "value": round(tap_macs / t_mig / 1e9, 4),
             "unit": "G complex tap-MAC/s",
@@ -255,10 +359,17 @@ def headline(torch, mig, synth, dev, args):
             "kind": "oracle",
             "sample": "the full workload (all 200 frequencies, 511 depth steps, unfolded "
                       "FP64 Eq. 1, OpenMP over frequencies), median of 3 runs; table "
-                      "design %.1f s not included" % t_design,
+                      "design %.1f s not included; one_core: the first 40 frequencies on "
+                      "one thread in a child process, scaled by 200/40" % t_design,
             "seconds": round(t_mig, 3),
+            "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "one_core": one,
         }
         res["speedup_vs_cpu_oracle"] = round(value / res["cpu_baseline"]["value"], 1)
+        if one and one.get("seconds"):
+            res["speedup_vs_cpu_oracle_one_core"] = round(value / (tap_macs / one["seconds"] / 1e9), 1)
+    res["config1"] = config1_line(torch, mig, synth, dev, args)
     ctx = {"sec": sec, "tab": tab, "data": data, "vel": vel, "omega": omega, "ws": ws,
            "ms_plain": ms_step}
     return res, ctx
@@ -275,7 +386,11 @@ def batched(torch, mig, synth, dev, args, profile=False):
     batch = [{"data": torch.from_numpy(s.data.astype(np.complex64)).to(dev),
               "vel": torch.from_numpy(s.vel).to(dev),
               "omega": torch.from_numpy(s.omega).to(dev)} for s in secs]
-    best, table = tune.autotune(batch, tab["tab32"], desc, reps=1)
+    if profile:
+        g, nred, qm = (int(v) for v in args.batched_tune.split(","))
+        best, table = {"omegas_per_group": g, "reducers": nred, "outputs_mid": qm}, []
+    else:
+        best, table = tune.autotune(batch, tab["tab32"], desc, reps=1)
     ws_b = torch.empty(max(mig.batch_workspace_size(batch, desc, best), 1), dtype=torch.uint8,
                        device=dev)
     reps = max(1, args.steps // 4)
@@ -310,6 +425,11 @@ def batched(torch, mig, synth, dev, args, profile=False):
         "G_tap_mac_per_s_plain": round(tap_macs / ms_p / 1e6, 1),
         "tune": best,
         "tune_candidates": len(table),
+        "tune_spread_pct": round(100.0 * (max(r["ms"] for r in table) /
+                                          min(r["ms"] for r in table) - 1.0), 2),
+        "tune_best_by_outputs_mid": {
+            str(q): round(min(r["ms"] for r in table if r["tune"]["outputs_mid"] == q), 3)
+            for q in (3, 4)},
         "images_bit_identical_to_plain": bool(same),
         "roofline": {
             "bound": "alu",
@@ -370,14 +490,27 @@ def adjoint(torch, mig, synth, dev, args, ctx=None, profile=False):
     rms = float(torch.sqrt(torch.mean(torch.abs(d_clean) ** 2)))
     noise = (torch.randn(d_clean.shape, generator=g) + 1j * torch.randn(d_clean.shape, generator=g))
     d_obs = d_clean + (0.05 * rms / np.sqrt(2.0) * noise).to(torch.complex64).to(dev)
+    lsm.cgls(d_obs, vel, omega, tab["tab32"], desc, niter=1)   # warm-up (first-use kernels)
     torch.cuda.synchronize()
     with Timer(torch) as t:
         m, hist = lsm.cgls(d_obs, vel, omega, tab["tab32"], desc, niter=10)
     err = float(torch.linalg.norm(m - refl) / torch.linalg.norm(refl))
-    # per point and step: (M+1) products conj(h) q (6 FLOP) and 2M complex
-    # additions of the gather (4M FLOP)
+    # what the operator can recover: CGLS from zero converges to the
+    # minimum-norm least-squares solution, so on the noise-free data it
+    # tends to the reflectivity projected onto the range of A (the part the
+    # 5-55 Hz band and the propagating wavenumbers carry); 200 iterations
+    m_rec, hist_rec = lsm.cgls(d_clean, vel, omega, tab["tab32"], desc, niter=200)
+    nrec = float(torch.linalg.norm(m_rec))
+    err_rec = float(torch.linalg.norm(m - m_rec)) / nrec
+    mig_img = mig.migrate(d_obs, vel, omega, tab["tab32"], desc)
+    sc = float(torch.sum(mig_img * m_rec) / torch.sum(mig_img * mig_img))
+    err_mig_rec = float(torch.linalg.norm(sc * mig_img - m_rec)) / nrec
+    sc_t = float(torch.sum(mig_img * refl) / torch.sum(mig_img * mig_img))
+    err_mig = float(torch.linalg.norm(sc_t * mig_img - refl) / torch.linalg.norm(refl))
+    # algorithmic FLOP as for migration: the folded Eq. (1) count per output
+    # and step (the corrections at lateral changes are overhead)
     M = (desc.ntaps - 1) // 2
-    flop_adj = nx * sec.nw * (nz - 1) * (6 * (M + 1) + 4 * M)
+    flop_adj = nx * sec.nw * (nz - 1) * (8 * (M + 1) + 2 * M)
     out = {
         "workload": "adjoint of the headline section's migration (reflectivity -> data), "
                     "and CGLS least-squares migration with 5 % Gaussian noise, 10 iterations",
@@ -386,18 +519,30 @@ def adjoint(torch, mig, synth, dev, args, ctx=None, profile=False):
         "adjoint_vs_plain_time": round(ms_adj / ms_fwd, 3),
         "dot_product_rel_err": dot_rel,
         "cgls_ms_total": round(t.ms, 2),
+        "cgls_ms_operators": round(11 * ms_fwd + 10 * ms_adj, 2),
         "cgls_residual_history": [round(h, 4) for h in hist],
         "cgls_model_rel_err": round(err, 4),
+        "best_scaled_migration_rel_err": round(err_mig, 4),
+        "recoverable": {
+            "definition": "CGLS, 200 iterations from zero on the noise-free data: the "
+                          "minimum-norm solution, i.e. the reflectivity projected onto the "
+                          "range of the migration operator",
+            "norm_fraction_of_true": round(nrec / float(torch.linalg.norm(refl)), 4),
+            "rel_residual_after_200": round(hist_rec[-1], 5),
+            "cgls10_rel_err_vs_recoverable": round(err_rec, 4),
+            "best_scaled_migration_rel_err_vs_recoverable": round(err_mig_rec, 4),
+        },
         "roofline": {
             "bound": "alu",
-            "kernel": "demigration launch (register-tap adjoint kernel, all depth steps) with "
-                      "its slowness pre-kernel",
+            "kernel": "demigration: slowness and change-point pre-kernels, the folded adjoint "
+                      "kernel (all depth steps; exact corrections at lateral changes) and the "
+                      "product kernel's immediate return",
             "achieved": round(flop_adj / (ms_adj * 1e-3) / 1e12, 3),
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(flop_adj / (ms_adj * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-            "flop_per_output": 6 * (M + 1) + 4 * M,
-            "traffic": None,
+            "flop_per_output": 8 * (M + 1) + 2 * M,
+            "traffic": profiled_traffic(args, "mig_demigrate config2"),
         },
     }
     print("adjoint: %.3f ms vs migrate %.3f ms; CGLS %.1f ms" % (ms_adj, ms_fwd, t.ms),
@@ -548,6 +693,9 @@ def transform(torch, mig, synth, dev, args, profile=False):
 
 def main():
     args = parse()
+    if args.oracle_one_core:
+        oracle_one_core_child()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU; runs over several GPUs are not supported "

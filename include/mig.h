@@ -332,6 +332,10 @@ typedef struct {
     int32_t stall_limit_us;   /* reducer stall limit in microseconds
                                  (0 = 20 s); see mig_workspace_status        */
     int32_t flags;            /* 0, or MIG_TUNE_FORCE_STALL                 */
+    int32_t outputs_mid;      /* outputs per thread of the register-tap
+                                 kernel for sections of 1025..1536 points:
+                                 3 (6-8 waves per frequency) or 4 (5-6
+                                 waves); 0 = library choice (3)              */
 } mig_tuning;
 
 /* Test hook for the failure path: reducers wait for one publish more than

@@ -117,6 +117,7 @@ struct Tuning {
     int nred = 0;           // reducer workgroups (0 = default)
     int stall_us = 0;       // reducer stall limit in microseconds (0 = default)
     int flags = 0;          // MIG_TUNE_* bits
+    int q_mid = 0;          // outputs per thread for 1025..1536 points (0 = 3)
 };
 
 Tuning tuning_of(const mig_tuning* t)
@@ -127,6 +128,7 @@ Tuning tuning_of(const mig_tuning* t)
         tn.nred = t->reducers;
         tn.stall_us = t->stall_limit_us;
         tn.flags = t->flags;
+        tn.q_mid = t->outputs_mid;
     }
     return tn;
 }
@@ -134,7 +136,16 @@ Tuning tuning_of(const mig_tuning* t)
 bool tuning_valid(const mig_tuning* t)
 {
     return !t || (t->omegas_per_group >= 0 && t->reducers >= 0 && t->stall_limit_us >= 0 &&
-                  (t->flags & ~MIG_TUNE_FORCE_STALL) == 0);
+                  (t->flags & ~MIG_TUNE_FORCE_STALL) == 0 &&
+                  (t->outputs_mid == 0 || t->outputs_mid == 3 || t->outputs_mid == 4));
+}
+
+// Kernel variant of a batched section: the library's choice, except that
+// sections of 1025..1536 points take the four-output kernel when tuned so.
+int batch_kernel_kind(int nx, int M, const Tuning& tn)
+{
+    const int kind = extrap_kernel_kind(nx, M);
+    return (kind == 3 && tn.q_mid == 4) ? 2 : kind;
 }
 
 // Calls that run no depth step still leave a defined status in a workspace
@@ -314,7 +325,7 @@ void plan_batch(const mig_section* secs, int nsec, const mig_table_desc* d, cons
     for (int i = 0; i < nsec; ++i) {
         const mig_section& q = secs[i];
         if (q.nz < 2) continue;
-        const int kind = extrap_kernel_kind(q.nx, M);
+        const int kind = batch_kernel_kind(q.nx, M, tn);
         BatchPlan::Group& g = P.group[kind];
         g.kind = kind;
         SecDev S = {};

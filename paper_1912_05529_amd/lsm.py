@@ -6,7 +6,7 @@ mig_demigrate is its exact transpose for the real inner product
 ``torch.autograd.Function`` objects (each one's backward is the other kernel),
 least-squares migration by CGLS, and depth checkpoints of the extrapolated
 wavefield.  All operator applications run in the library's kernels; the CG
-vector updates are elementwise tensor arithmetic between iterations.
+vector updates and scalars are device tensor arithmetic between them.
 """
 from __future__ import annotations
 
@@ -57,17 +57,24 @@ def demigrate_fn(image, vel, omega, tab32, desc):
 
 
 def _dot_data(a, b):
-    return float(torch.sum(a.real.double() * b.real.double() + a.imag.double() * b.imag.double()))
+    """Re <a, b> on planes, as a 0-d float64 device tensor (no host sync)."""
+    return torch.sum(a.real.double() * b.real.double() + a.imag.double() * b.imag.double())
 
 
 def _dot_img(a, b):
-    return float(torch.sum(a * b))
+    return torch.sum(a * b)
 
 
 def cgls(d_obs, vel, omega, tab32, desc, niter=10, m0=None):
     """Least-squares migration: minimize ||A^T m - d_obs||^2 over real images m
     ([nz][nx] float64) by conjugate gradients on the normal equations (CGLS),
     with modelling A^T = mig_demigrate and its adjoint A = mig_migrate.
+
+    The CG scalars stay on the device (0-d tensors), so the iterations queue
+    without host round trips; the history is read back once at the end.
+    Started from zero, CGLS converges to the minimum-norm least-squares
+    solution, i.e. for noise-free data to the part of the true model that the
+    operator can recover (its projection onto the range of A).
 
     Returns (m, history) where history holds ||r|| / ||d_obs|| per iteration."""
     nz, nx = vel.shape
@@ -80,22 +87,23 @@ def cgls(d_obs, vel, omega, tab32, desc, niter=10, m0=None):
     s = mig.migrate(r, vel, omega, tab32, desc)
     p = s.clone()
     gamma = _dot_img(s, s)
-    dn = _dot_data(d_obs, d_obs) ** 0.5
-    hist = [_dot_data(r, r) ** 0.5 / dn]
+    dn = torch.sqrt(_dot_data(d_obs, d_obs))
+    hist = [torch.sqrt(_dot_data(r, r)) / dn]
+    zero = torch.zeros((), dtype=torch.float64, device=d_obs.device)
     for _ in range(niter):
         q = mig.demigrate(p, vel, omega, tab32, desc)
         qq = _dot_data(q, q)
-        if qq == 0.0:
-            break
-        alpha = gamma / qq
+        # a zero direction (converged exactly) leaves everything unchanged
+        alpha = torch.where(qq > 0, gamma / torch.where(qq > 0, qq, 1.0), zero)
         m = m + alpha * p
         r = (r - alpha * q).to(torch.complex64)
         s = mig.migrate(r, vel, omega, tab32, desc)
         gnew = _dot_img(s, s)
-        p = s + (gnew / gamma) * p
+        beta = torch.where(gamma > 0, gnew / torch.where(gamma > 0, gamma, 1.0), zero)
+        p = s + beta * p
         gamma = gnew
-        hist.append(_dot_data(r, r) ** 0.5 / dn)
-    return m, hist
+        hist.append(torch.sqrt(_dot_data(r, r)) / dn)
+    return m, [float(h) for h in torch.stack(hist).cpu()]
 
 
 def migrate_checkpointed(data, vel, omega, tab32, desc, every=32, ws=None):

@@ -57,7 +57,8 @@ class CTuning(C.Structure):
     """ctypes mirror of ``mig_tuning``."""
 
     _fields_ = [("omegas_per_group", C.c_int32), ("reducers", C.c_int32),
-                ("stall_limit_us", C.c_int32), ("flags", C.c_int32)]
+                ("stall_limit_us", C.c_int32), ("flags", C.c_int32),
+                ("outputs_mid", C.c_int32)]
 
 
 MIG_TUNE_FORCE_STALL = 1
@@ -328,6 +329,7 @@ def _tuning(tune):
     t.reducers = int(tune.get("reducers", 0))
     t.stall_limit_us = int(tune.get("stall_limit_us", 0))
     t.flags = int(tune.get("flags", 0))
+    t.outputs_mid = int(tune.get("outputs_mid", 0))
     return C.byref(t)
 
 

@@ -2,11 +2,15 @@
 
 The knobs are the ones the depth-stepping launch exposes (mig_tuning):
 frequencies per workgroup in the two-output register-tap kernel (how many
-frequency columns share a workgroup when nx is small) and the number of
-reducer workgroups that form image rows beside the frequency workgroups.
-Depth fusion is not a knob: all depth steps of a section always run in one
-launch.  Each candidate is timed with HIP events on the current stream; the
-result is cached per batch shape for the life of the process.
+frequency columns share a workgroup when nx is small), outputs per thread
+for sections of 1025..1536 points (three: 6-8 waves per frequency, or four:
+5-6 waves with more work each; the x-tile of a workgroup is always the whole
+section width, so this is the tile knob), and the number of reducer
+workgroups that form image rows beside the frequency workgroups.  Depth
+fusion is not a knob: all depth steps of a section always run in one launch
+(the plane never leaves LDS), which is the most fusion there is.  Each
+candidate is timed with HIP events on the current stream; the result is
+cached per batch shape for the life of the process.
 """
 from __future__ import annotations
 
@@ -19,7 +23,8 @@ from . import mig
 _cache: dict = {}
 
 OMEGAS_PER_GROUP = (1, 2, 4, 8)
-REDUCERS = (0, 16, 24, 32, 48, 64)
+REDUCERS = (16, 32, 48)
+OUTPUTS_MID = (3, 4)
 
 
 def signature(batch, desc) -> tuple:
@@ -33,8 +38,8 @@ def autotune(batch, tab32, desc, candidates=None, reps: int = 2, use_cache: bool
     if use_cache and key in _cache:
         return _cache[key]
     if candidates is None:
-        candidates = [{"omegas_per_group": g, "reducers": r}
-                      for g, r in itertools.product(OMEGAS_PER_GROUP, REDUCERS)]
+        candidates = [{"omegas_per_group": g, "reducers": r, "outputs_mid": q}
+                      for g, r, q in itertools.product(OMEGAS_PER_GROUP, REDUCERS, OUTPUTS_MID)]
     need = max(mig.batch_workspace_size(batch, desc, c) for c in candidates)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=tab32.device)
     stream = torch.cuda.current_stream()

@@ -99,10 +99,13 @@ def test_batched_tuning_is_validated_on_the_host(L):
     d = mig.cdesc(_desc())
     sec = (mig.CSection * 1)()
     sec[0] = mig.CSection(4096, 8192, 12288, 16384, 64, 8, 4, 0)
-    ok = mig.CTuning(0, 0, 0, 0)
+    ok = mig.CTuning(0, 0, 0, 0, 0)
     assert L.mig_batch_workspace_size(sec, 1, C.byref(d), C.byref(ok)) > 0
-    for bad in (mig.CTuning(-1, 0, 0, 0), mig.CTuning(0, -2, 0, 0), mig.CTuning(0, 0, -5, 0),
-                mig.CTuning(0, 0, 0, 2)):
+    for q in (3, 4):
+        assert L.mig_batch_workspace_size(sec, 1, C.byref(d), C.byref(mig.CTuning(0, 0, 0, 0, q))) > 0
+    for bad in (mig.CTuning(-1, 0, 0, 0, 0), mig.CTuning(0, -2, 0, 0, 0),
+                mig.CTuning(0, 0, -5, 0, 0), mig.CTuning(0, 0, 0, 2, 0),
+                mig.CTuning(0, 0, 0, 0, 2), mig.CTuning(0, 0, 0, 0, 5)):
         assert L.mig_batch_workspace_size(sec, 1, C.byref(d), C.byref(bad)) == 0
         assert L.mig_migrate_batched(sec, 1, fake, C.byref(d), C.byref(bad), fake, 1 << 30,
                                      None) == -1

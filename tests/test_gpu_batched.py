@@ -74,6 +74,24 @@ def test_batched_tuning_does_not_change_results(mixed, tune):
         assert np.array_equal(a, b)
 
 
+def test_four_outputs_for_mid_widths_matches_oracle(mixed):
+    """outputs_mid = 4 runs sections of 1025..1536 points on the four-output
+    kernel: that section against the FP64 oracle element by element (another
+    kernel variant: FP32 rounding may differ from the three-output kernel's),
+    every other section bit-identical to the default tuning."""
+    secs, desc, tab = mixed
+    ot = oracle.design_table(desc)[0]
+    base = _run_batched(secs, desc, tab)
+    got = _run_batched(secs, desc, tab, {"outputs_mid": 4})
+    for s, a, g in zip(secs, base, got):
+        if 1025 <= s.nx <= 1536 and s.nz > 1:
+            ref = oracle.migrate(desc, ot, s.omega, s.vel, data64(s))
+            assert_rows_close(g, ref, 1e-5, "outputs_mid=4 " + s.name)
+            assert rel_l2(g, a) <= 1e-6
+        else:
+            assert np.array_equal(a, g), s.name
+
+
 def test_batched_matches_oracle(mixed):
     secs, desc, tab = mixed
     ot = oracle.design_table(desc)[0]
