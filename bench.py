@@ -369,7 +369,8 @@ def headline(torch, mig, synth, dev, args):
         res["speedup_vs_cpu_oracle"] = round(value / res["cpu_baseline"]["value"], 1)
         if one and one.get("seconds"):
             res["speedup_vs_cpu_oracle_one_core"] = round(value / (tap_macs / one["seconds"] / 1e9), 1)
-    res["config1"] = config1_line(torch, mig, synth, dev, args)
+    if not args.profile:
+        res["config1"] = config1_line(torch, mig, synth, dev, args)
     ctx = {"sec": sec, "tab": tab, "data": data, "vel": vel, "omega": omega, "ws": ws,
            "ms_plain": ms_step}
     return res, ctx
@@ -439,7 +440,10 @@ def batched(torch, mig, synth, dev, args, profile=False):
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(flop / (ms_b * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-            "traffic": None,
+            "traffic": profiled_traffic(args, "mig_migrate_batched config3"),
+            "traffic_note": "HBM bytes per batched call (tuning 2, 32, 4), mostly the partial "
+                            "image rows: 4 B per output written and read, rows padded to 256 "
+                            "points",
         },
     }
     print("batched: %.3f ms vs plain %.3f ms (%s)" % (ms_b, ms_p, best), file=sys.stderr,
@@ -667,7 +671,7 @@ def transform(torch, mig, synth, dev, args, profile=False):
             "unit": "TFLOP/s",
             "frac": round(flop / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
             "flop_per_launch": flop,
-            "traffic": None,
+            "traffic": profiled_traffic(args, "mig_transform_t 1024x1024x200"),
         },
     }
     if not args.no_cpu_baseline:
