@@ -327,8 +327,8 @@ typedef struct {
                                  512 threads); clamped to what fits          */
     int32_t reducers;         /* reducer workgroups per launch, 8..64
                                  (0 = the CUs the frequency workgroups leave
-                                 idle, at least 8); never more than a quarter
-                                 of the device's CUs                         */
+                                 idle, at least 8 and at most 32); never more
+                                 than a quarter of the device's CUs          */
     int32_t stall_limit_us;   /* reducer stall limit in microseconds
                                  (0 = 20 s); see mig_workspace_status        */
     int32_t flags;            /* 0, or MIG_TUNE_FORCE_STALL                 */
