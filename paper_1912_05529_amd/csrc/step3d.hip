@@ -341,10 +341,57 @@ k_step3d(Step3dArgs A)
     const int y = y0 + lane;
     const int r0 = wave * kRows3;
 
-    for (int e = threadIdx.x; e < kTileX3 * kLanes3; e += kThreads3) {
+    const int wbeg = g * A.wpg;
+    const int wend = wbeg + A.wpg < A.nw ? wbeg + A.wpg : A.nw;
+    const int pbytes = (int)(plane * sizeof(float2));
+    // The first tile's copy goes out first; the velocity and previous-image
+    // loads below are all issued before any of them is waited for, so the
+    // prologue costs about one memory latency, not one per load.
+    stage_rows<M>(T[0], __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)wbeg * plane), 0,
+                                                         pbytes, kRawBufferWord3),
+                  x0, y0, A.ny, wave, lane);
+
+    constexpr int kPer3 = kTileX3 * kLanes3 / kThreads3;  // tile points per thread
+    float vv[kPer3];
+#pragma unroll
+    for (int i = 0; i < kPer3; ++i) {
+        const int e = threadIdx.x + i * kThreads3;
         const int x = x0 + e / kLanes3, yy = y0 + e % kLanes3;
-        S[e] = (x < A.nx && yy < A.ny) ? slowness_of(A.vel[(size_t)x * A.ny + yy])
-                                       : __builtin_nan("");
+        vv[i] = (x < A.nx && yy < A.ny) ? A.vel[(size_t)x * A.ny + yy] : 0.0f;
+    }
+
+    // Image row of the previous depth step: this workgroup's share of the
+    // tile, groups added in group order (the partials of the previous launch
+    // are complete when this one starts).
+    if (A.prev) {
+        constexpr int pts = kTileX3 * kLanes3;
+        constexpr int kBatch = 8;  // partial loads in flight per thread
+        const int share = (pts + A.ngroups - 1) / A.ngroups;
+        const int e1 = (g + 1) * share < pts ? (g + 1) * share : pts;
+        for (int e = g * share + threadIdx.x; e < e1; e += kThreads3) {
+            const int x = x0 + e / kLanes3, yy = y0 + e % kLanes3;
+            if (x < A.nx && yy < A.ny) {
+                const size_t p = (size_t)x * A.ny + yy;
+                double s = 0.0;
+                for (int q0 = 0; q0 < A.ngroups; q0 += kBatch) {
+                    double pv[kBatch];
+#pragma unroll
+                    for (int i = 0; i < kBatch; ++i)
+                        pv[i] = q0 + i < A.ngroups ? A.prev[(size_t)(q0 + i) * plane + p] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < kBatch; ++i)
+                        if (q0 + i < A.ngroups) s += pv[i];
+                }
+                A.prev_row[p] = s;
+            }
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < kPer3; ++i) {
+        const int e = threadIdx.x + i * kThreads3;
+        const int x = x0 + e / kLanes3, yy = y0 + e % kLanes3;
+        S[e] = (x < A.nx && yy < A.ny) ? slowness_of(vv[i]) : __builtin_nan("");
     }
 
     double img[kRows3];
@@ -357,14 +404,13 @@ k_step3d(Step3dArgs A)
     // past nx land past the plane's end by themselves; a column past ny is
     // moved out of range as a whole (stores out of range are dropped).
     const int qbase = y < A.ny ? (x0 + r0) * ny8 + y * 8 : 0x40000000;
-    const int pbytes = (int)(plane * sizeof(float2));
 
-    const int wbeg = g * A.wpg;
-    const int wend = wbeg + A.wpg < A.nw ? wbeg + A.wpg : A.nw;
-    stage_rows<M>(T[0], __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)wbeg * plane), 0,
-                                                         pbytes, kRawBufferWord3),
-                  x0, y0, A.ny, wave, lane);
-    double om = A.omega[wbeg];  // frequency of the coming iteration, loaded one ahead
+    // Frequencies are read through the constant address space: uniform loads
+    // of read-only data become scalar loads, so waiting for one never waits for
+    // the vector-memory operations in flight (tile copies, output stores).
+    typedef const __attribute__((address_space(4))) double* const_f64_ptr;
+    const const_f64_ptr omc = (const_f64_ptr)A.omega;
+    double om = omc[wbeg];  // frequency of the coming iteration, loaded one ahead
     for (int w = wbeg; w < wend; ++w) {
         const int cur = (w - wbeg) & 1;
         float2* Tb = T[cur];
@@ -379,7 +425,7 @@ k_step3d(Step3dArgs A)
             wait_vmem_but_rows();
         barrier_lds();
         const double ar = om / A.dk;
-        if (w + 1 < wend) om = A.omega[w + 1];
+        if (w + 1 < wend) om = omc[w + 1];
         int jrow[kRows3];
 #pragma unroll
         for (int r = 0; r < kRows3; ++r)
@@ -419,23 +465,6 @@ k_step3d(Step3dArgs A)
         const int x = x0 + r0 + r;
         if (x < A.nx && y < A.ny) A.part[(size_t)g * plane + (size_t)x * A.ny + y] = img[r];
     }
-
-    // Image row of the previous depth step: this workgroup's share of the
-    // tile, groups added in group order.
-    if (A.prev) {
-        constexpr int pts = kTileX3 * kLanes3;
-        const int share = (pts + A.ngroups - 1) / A.ngroups;
-        const int e1 = (g + 1) * share < pts ? (g + 1) * share : pts;
-        for (int e = g * share + threadIdx.x; e < e1; e += kThreads3) {
-            const int x = x0 + e / kLanes3, yy = y0 + e % kLanes3;
-            if (x < A.nx && yy < A.ny) {
-                const size_t p = (size_t)x * A.ny + yy;
-                double s = 0.0;
-                for (int q = 0; q < A.ngroups; ++q) s += A.prev[(size_t)q * plane + p];
-                A.prev_row[p] = s;
-            }
-        }
-    }
 }
 
 // Image of a plane: row[p] = sum over frequencies, in order, of Re wf[w][p].
@@ -445,7 +474,14 @@ __global__ void k_image3d(const float2* __restrict__ wf, double* __restrict__ ro
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane;
          p += (size_t)gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += (double)wf[(size_t)w * plane + p].x;
+        for (int w0 = 0; w0 < nw; w0 += 16) {
+            float v[16];  // loads in flight, summed in frequency order
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = w0 + i < nw ? wf[(size_t)(w0 + i) * plane + p].x : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (w0 + i < nw) s += (double)v[i];
+        }
         row[p] = s;
     }
 }
@@ -457,7 +493,14 @@ __global__ void k_reduce3d(const double* __restrict__ part, double* __restrict__
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane;
          p += (size_t)gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int q = 0; q < ngroups; ++q) s += part[(size_t)q * plane + p];
+        for (int q0 = 0; q0 < ngroups; q0 += 16) {
+            double v[16];  // loads in flight, summed in group order
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = q0 + i < ngroups ? part[(size_t)(q0 + i) * plane + p] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (q0 + i < ngroups) s += v[i];
+        }
         row[p] = s;
     }
 }
