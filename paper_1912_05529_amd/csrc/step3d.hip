@@ -170,12 +170,14 @@ struct Acc3 {
 // The last pass also finishes each output at once: Re into the image
 // partial, and a buffer store whose offset is pushed out of range for
 // points outside the volume (so no output waits behind a branch).
-template <int M, int LO, int HI, bool LAST>
+// `issue(i)` runs at the start of row i of the pass (the last pass uses it
+// to copy the next frequency's tile a few rows at a time).
+template <int M, int LO, int HI, bool LAST, typename Issue>
 __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const int (&jrow)[kRows3],
                                          float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)], int& jcur,
                                          __amdgpu_buffer_rsrc_t rt, float2 (&acc)[kRows3],
                                          double (&img)[kRows3], __amdgpu_buffer_rsrc_t rq,
-                                         int qbase, int ny8)
+                                         int qbase, int ny8, Issue&& issue)
 {
     constexpr int W = kLanes3 + 2 * M;
     constexpr int NP = HI - LO;
@@ -204,6 +206,7 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const in
     fetch(std::integral_constant<int, 0>{});
     static_for<0, NR>([&](auto I) {
         constexpr int i = decltype(I)::value;
+        issue(I);
         if constexpr (i + 1 < NR) fetch(std::integral_constant<int, i + 1>{});
         static_for<0, NP>([&](auto Q) {
             constexpr int q = decltype(Q)::value;
@@ -283,29 +286,38 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // the 2 (64 + 2M) dwords of columns y0 - M .. y0 + 63 + M, 64 dwords per
 // instruction.  Rows outside [0, nx) lie outside the buffer and arrive as
 // zeros; so do columns outside [0, ny), whose lanes read at an offset pushed
-// out of range (the same for every row).
+// out of range (the same for every row).  A call copies this wave's rows
+// q in [Q0, Q1), q-th row of the wave being tile row q * 4 + wave.
 template <int M>
-__device__ __forceinline__ void stage_rows(float2* Tb, __amdgpu_buffer_rsrc_t rp, int x0, int y0,
+constexpr int stage_chunks() { return (2 * (kLanes3 + 2 * M) + 63) / 64; }
+
+// Per-lane offset bias of each 64-dword chunk of a row (columns outside the
+// volume pushed out of range); the same for every row and frequency.
+template <int M>
+__device__ __forceinline__ void stage_bias(int (&bias)[stage_chunks<M>()], int y0, int ny, int lane)
+{
+    static_for<0, stage_chunks<M>()>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int yc = y0 - M + (i * 64 + lane) / 2;  // column of this lane's dword
+        bias[i] = (unsigned)yc < (unsigned)ny ? 0 : 0x40000000;
+    });
+}
+
+template <int M, int Q0, int Q1>
+__device__ __forceinline__ void stage_rows(float2* Tb, __amdgpu_buffer_rsrc_t rp,
+                                           const int (&bias)[stage_chunks<M>()], int x0, int y0,
                                            int ny, int wave, int lane)
 {
     constexpr int W = kLanes3 + 2 * M;
-    constexpr int H = kTileX3 + 2 * M;
-    constexpr int HP = (H + kWaves3 - 1) / kWaves3 * kWaves3;
     constexpr int DW = 2 * W;  // dwords per row
     // wave, x0, y0 and ny are wave-uniform: row offsets and LDS destinations
     // are scalar; one vector add per row, chunks of 64 dwords by the
     // instruction's immediate offset, which applies to the global and the LDS
     // address alike (so the LDS base stays at the row start).
     const int lane4 = lane * 4;
-    constexpr int NCH = (DW + 63) / 64;
-    int bias[NCH];
-    static_for<0, NCH>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const int yc = y0 - M + (i * 64 + lane) / 2;  // column of this lane's dword
-        bias[i] = (unsigned)yc < (unsigned)ny ? 0 : 0x40000000;
-    });
+    constexpr int NCH = stage_chunks<M>();
 #pragma unroll
-    for (int q = 0; q < HP / kWaves3; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
         const int r = q * kWaves3 + wave;
         const int voff = ((x0 - M + r) * ny + (y0 - M)) * 8 + lane4;
         char* dst = reinterpret_cast<char*>(Tb + r * W);
@@ -328,6 +340,7 @@ k_step3d(Step3dArgs A)
     constexpr int SPLIT = M >= 3 ? (M + 1) / 2 : M + 1;  // planes of the first pass
     constexpr int NC1 = pass_slot(M, 0, SPLIT, M + 1, 0);
     constexpr int NC2 = pass_slot(M, SPLIT, M + 1, M + 1, 0);
+    constexpr int QW = HP / kWaves3;       // tile rows copied by each wave
     __shared__ float2 T[2][HP * W];            // double-buffered frequency tiles
     __shared__ double S[kTileX3 * kLanes3];
 
@@ -347,9 +360,11 @@ k_step3d(Step3dArgs A)
     // The first tile's copy goes out first; the velocity and previous-image
     // loads below are all issued before any of them is waited for, so the
     // prologue costs about one memory latency, not one per load.
-    stage_rows<M>(T[0], __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)wbeg * plane), 0,
-                                                         pbytes, kRawBufferWord3),
-                  x0, y0, A.ny, wave, lane);
+    int bias[stage_chunks<M>()];
+    stage_bias<M>(bias, y0, A.ny, lane);
+    stage_rows<M, 0, QW>(T[0], __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)wbeg * plane),
+                                                                0, pbytes, kRawBufferWord3),
+                         bias, x0, y0, A.ny, wave, lane);
 
     constexpr int kPer3 = kTileX3 * kLanes3 / kThreads3;  // tile points per thread
     float vv[kPer3];
@@ -430,18 +445,29 @@ k_step3d(Step3dArgs A)
 #pragma unroll
         for (int r = 0; r < kRows3; ++r)
             jrow[r] = index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
-        // First taps of the first pass, requested before the next tile's copy
-        // so that waiting for them does not wait for the copy (loads complete
-        // in order).
+        // First taps of the first pass.  Vector-memory operations complete in
+        // issue order, so a tap load issued after the next tile's copy would
+        // wait for that copy: the copy is issued during the last pass instead,
+        // one tile row per row of that pass's first 2M rows (the rows of pair
+        // sums before its first output), and only tap reloads in the last
+        // pass's output rows can wait for it.
         float2 h1[NC1];
         int j1 = jrow[0];
         load_pass_taps<M, 0, SPLIT>(h1, rt, j1);
-        __asm__ volatile("" ::: "memory");
-        if (w + 1 < wend)
-            stage_rows<M>(T[cur ^ 1],
-                          __builtin_amdgcn_make_buffer_rsrc((void*)(A.in + (size_t)(w + 1) * plane),
-                                                            0, pbytes, kRawBufferWord3),
-                          x0, y0, A.ny, wave, lane);
+        const bool more = w + 1 < wend;
+        const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(A.in + (size_t)(more ? w + 1 : w) * plane), 0, pbytes, kRawBufferWord3);
+        float2* Tn = T[cur ^ 1];
+        auto copy_next = [&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int PRE = 2 * M > 0 ? 2 * M : 1;  // rows of the pass carrying the copy
+            constexpr int q0 = i < PRE ? i : QW;
+            constexpr int q1 = i + 1 < PRE ? (i + 1 < QW ? i + 1 : QW) : (i < PRE ? QW : 0);
+            if constexpr (q0 < q1) {
+                if (more) stage_rows<M, q0, q1>(Tn, rn, bias, x0, y0, A.ny, wave, lane);
+            }
+        };
+        auto no_copy = [](auto) {};
 
         const float2* Tw = Tb + r0 * W + lane + M;  // tile row of x0 + r0 - M, column y
         const __amdgpu_buffer_rsrc_t rq =
@@ -451,12 +477,13 @@ k_step3d(Step3dArgs A)
 #pragma unroll
         for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
         if constexpr (SPLIT <= M) {
-            fir_pass<M, 0, SPLIT, false>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8);
+            fir_pass<M, 0, SPLIT, false>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8, no_copy);
             float2 h2[NC2];
             int j2 = -1;
-            fir_pass<M, SPLIT, M + 1, true>(Tw, jrow, h2, j2, rt, acc, img, rq, qbase, ny8);
+            fir_pass<M, SPLIT, M + 1, true>(Tw, jrow, h2, j2, rt, acc, img, rq, qbase, ny8,
+                                            copy_next);
         } else {
-            fir_pass<M, 0, M + 1, true>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8);
+            fir_pass<M, 0, M + 1, true>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8, copy_next);
         }
     }
 
