@@ -30,6 +30,7 @@
 // adds the groups' partials in group order (so no atomics and no waiting), and
 // a last small kernel closes the final step.  Results are deterministic for a
 // given frequency grouping.
+#include <cstddef>
 #include <type_traits>
 
 #include "common.hpp"
@@ -42,6 +43,9 @@ constexpr int kWaves3 = 4;                   // waves per workgroup
 constexpr int kRows3 = 8;                    // x rows walked by each wave
 constexpr int kTileX3 = kWaves3 * kRows3;    // x rows per tile
 constexpr int kThreads3 = kWaves3 * 64;
+constexpr int kSlots3 = 4;                   // LDS tap slots per wave (see k_step3d)
+constexpr int kSlotF2 = 32;                  // complex values per slot (>= unique taps)
+constexpr int kNoSlot = 7;                   // 3-bit slot code of a point without a slot
 
 // Buffer resource word 3 for raw (unformatted, unswizzled) buffers on the
 // gfx9 family; loads beyond num_records return zero.
@@ -160,6 +164,46 @@ __device__ __forceinline__ void load_pass_taps(float2 (&h)[pass_slot(M, LO, HI, 
     });
 }
 
+// The same taps from an LDS slot holding the NU unique coefficients of one
+// table entry (in coefficient order).
+template <int M, int LO, int HI>
+__device__ __forceinline__ void lds_pass_taps(float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)],
+                                              const float2* slot)
+{
+    static_for<0, M + 1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        static_for<0, a + 1>([&](auto BB) {
+            constexpr int b = decltype(BB)::value;
+            if constexpr (in_set(a, LO, HI) || in_set(b, LO, HI))
+                h[pass_slot(M, LO, HI, a, b)] = slot[cidx(a, b)];
+        });
+    });
+}
+
+__device__ __forceinline__ int slot_of(unsigned slots, int r) { return (slots >> (3 * r)) & 7u; }
+
+// Where taps come from.  With SLOTS, a row's key is the point's slot and its
+// taps come from the wave's LDS slots (TSw); otherwise the key is the table
+// entry and the taps come from the table.  The two forms are separate code
+// paths (a workgroup takes one for all its frequencies), so that the slot
+// path issues no tap load to memory: the compiler's waits after a load that
+// may or may not have been issued are conservative and would also wait for
+// the tile copy in flight.
+struct TapSrc {
+    const float2* TSw;
+    __amdgpu_buffer_rsrc_t rt;
+};
+
+template <int M, int LO, int HI, bool SLOTS>
+__device__ __forceinline__ void row_taps(float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)],
+                                         const TapSrc& ts, int key)
+{
+    if constexpr (SLOTS)
+        lds_pass_taps<M, LO, HI>(h, ts.TSw + key * kSlotF2);
+    else
+        load_pass_taps<M, LO, HI>(h, ts.rt, key);
+}
+
 // Partial output of a pass: Re = re1 - re2 with re1 = sum Re h Re s and
 // re2 = sum Im h Im s kept apart (no negated operands), Im = sum of the
 // cross products.
@@ -172,12 +216,15 @@ struct Acc3 {
 // points outside the volume (so no output waits behind a branch).
 // `issue(i)` runs at the start of row i of the pass (the last pass uses it
 // to copy the next frequency's tile a few rows at a time).
-template <int M, int LO, int HI, bool LAST, typename Issue>
-__device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const int (&jrow)[kRows3],
-                                         float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)], int& jcur,
-                                         __amdgpu_buffer_rsrc_t rt, float2 (&acc)[kRows3],
-                                         double (&img)[kRows3], __amdgpu_buffer_rsrc_t rq,
-                                         int qbase, int ny8, Issue&& issue)
+// Taps are reloaded at a row where some lane's key (slot or table entry,
+// keys[r]) differs from the one its registers hold (kcur).
+template <int M, int LO, int HI, bool LAST, bool PRELOADED, bool SLOTS, typename Issue>
+__device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const TapSrc& ts,
+                                         const int (&keys)[kRows3],
+                                         float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)], int& kcur,
+                                         float2 (&acc)[kRows3], double (&img)[kRows3],
+                                         __amdgpu_buffer_rsrc_t rq, int qbase, int ny8,
+                                         Issue&& issue)
 {
     constexpr int W = kLanes3 + 2 * M;
     constexpr int NP = HI - LO;
@@ -197,11 +244,12 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const in
             if constexpr (b != 0) v[i & 1][2 * q + 1] = row[-b];
         });
     };
-    // Taps of the first output row, requested before the 2M rows of pair sums
-    // that precede it, so their latency hides behind those rows.
-    if (__builtin_amdgcn_ballot_w64(jrow[0] != jcur) != 0) {
-        load_pass_taps<M, LO, HI>(h, rt, jrow[0]);
-        jcur = jrow[0];
+    // Taps of the first output row (unless the caller has them), requested
+    // before the 2M rows of pair sums that precede it, so their latency hides
+    // behind those rows.
+    if constexpr (!PRELOADED) {
+        row_taps<M, LO, HI, SLOTS>(h, ts, keys[0]);
+        kcur = keys[0];
     }
     fetch(std::integral_constant<int, 0>{});
     static_for<0, NR>([&](auto I) {
@@ -222,10 +270,9 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const in
         if constexpr (i >= 2 * M) {
             constexpr int r = i - 2 * M;  // output row x0 + r0 + r
             constexpr int c = r + M;      // its pair sums
-            const int j = jrow[r];
-            if (__builtin_amdgcn_ballot_w64(j != jcur) != 0) {
-                load_pass_taps<M, LO, HI>(h, rt, j);
-                jcur = j;
+            if (__builtin_amdgcn_ballot_w64(keys[r] != kcur) != 0) {
+                row_taps<M, LO, HI, SLOTS>(h, ts, keys[r]);
+                kcur = keys[r];
             }
             Acc3 o{acc[r].x, 0.0f, acc[r].y};
             static_for<0, M + 1>([&](auto AA) {
@@ -341,8 +388,24 @@ k_step3d(Step3dArgs A)
     constexpr int NC1 = pass_slot(M, 0, SPLIT, M + 1, 0);
     constexpr int NC2 = pass_slot(M, SPLIT, M + 1, M + 1, 0);
     constexpr int QW = HP / kWaves3;       // tile rows copied by each wave
-    __shared__ float2 T[2][HP * W];            // double-buffered frequency tiles
-    __shared__ double S[kTileX3 * kLanes3];
+    // LDS in one block, in this order: the targets of buffer-to-LDS copies
+    // (tap slots, tiles) come first and stay within the low 64 KiB.
+    struct Lds {
+        float2 TS[2][kWaves3 * kSlots3 * kSlotF2];  // tap slots, by frequency parity
+        float2 T[2][HP * W];                        // double-buffered frequency tiles
+        double S[kTileX3 * kLanes3];                // slowness of the tile
+        double SL[kWaves3 * kSlots3];               // slowness of each slot
+        int FB[kWaves3];                            // wave has points without a slot
+    };
+    static_assert(offsetof(Lds, S) <= 65536, "copy targets below 64 KiB");
+    __shared__ Lds L;
+    auto& TS = L.TS;
+    auto& T = L.T;
+    auto& S = L.S;
+    auto& SL = L.SL;
+    auto& FB = L.FB;
+    constexpr int NU = (M + 1) * (M + 2) / 2;
+    static_assert(NU <= kSlotF2, "tap slot size");
 
     const int ntiles = A.tiles_x * A.tiles_y;
     const int bid = logical_block();
@@ -357,6 +420,8 @@ k_step3d(Step3dArgs A)
     const int wbeg = g * A.wpg;
     const int wend = wbeg + A.wpg < A.nw ? wbeg + A.wpg : A.nw;
     const int pbytes = (int)(plane * sizeof(float2));
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)A.tab, 0, A.nk * NU * (int)sizeof(float2), kRawBufferWord3);
     // The first tile's copy goes out first; the velocity and previous-image
     // loads below are all issued before any of them is waited for, so the
     // prologue costs about one memory latency, not one per load.
@@ -409,11 +474,72 @@ k_step3d(Step3dArgs A)
         S[e] = (x < A.nx && yy < A.ny) ? slowness_of(vv[i]) : __builtin_nan("");
     }
 
+    barrier_lds();  // the wave's slowness rows were written by other waves
+
+    // Tap slots.  A point's table entry is a function of its slowness, so
+    // points of equal slowness share the entry at every frequency, and a wave
+    // of a layered volume sees only a few distinct slowness values (a layer,
+    // two across an interface).  Each of the first kSlots3 distinct values of
+    // the wave's 8 x 64 points gets a slot in LDS holding its entry's taps;
+    // per frequency the slots are refilled by buffer-to-LDS copies issued one
+    // frequency ahead, so a change of entry between rows reads LDS instead of
+    // waiting for L2 (and, vector-memory operations completing in order, for
+    // every copy in flight).  A workgroup with a point beyond the slots
+    // loads every tap from the table instead.  Values are compared by bit
+    // pattern (one NaN for every point without a velocity).
+    unsigned slots = 0xFFFFFFu;  // 3 bits per row, kNoSlot = none
+    int nsl = 0;
+    {
+        unsigned long long pat[kRows3];
+#pragma unroll
+        for (int r = 0; r < kRows3; ++r)
+            pat[r] = (unsigned long long)__double_as_longlong(S[(r0 + r) * kLanes3 + lane]);
+        for (int k = 0; k < kSlots3; ++k) {
+            unsigned long long key = 0;
+            bool found = false;
+#pragma unroll
+            for (int r = 0; r < kRows3; ++r) {
+                const unsigned long long m =
+                    __builtin_amdgcn_ballot_w64(slot_of(slots, r) == kNoSlot);
+                if (!found && m != 0) {
+                    const int l = __builtin_ctzll(m);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(pat[r] >> 32), l);
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)pat[r], l);
+                    key = ((unsigned long long)hi << 32) | lo;
+                    found = true;
+                }
+            }
+            if (!found) break;
+#pragma unroll
+            for (int r = 0; r < kRows3; ++r)
+                if (slot_of(slots, r) == kNoSlot && pat[r] == key)
+                    slots = (slots & ~(7u << (3 * r))) | ((unsigned)k << (3 * r));
+            if (lane == 0) SL[wave * kSlots3 + k] = __longlong_as_double((long long)key);
+            nsl = k + 1;
+        }
+    }
+    // One path per workgroup: slots when every point of every wave has one.
+    bool none = false;
+#pragma unroll
+    for (int r = 0; r < kRows3; ++r) none = none || slot_of(slots, r) == kNoSlot;
+    const bool wave_none = __builtin_amdgcn_ballot_w64(none) != 0;  // all lanes vote
+    if (lane == 0) FB[wave] = wave_none ? 1 : 0;
+    barrier_lds();
+    const bool use_slots = (FB[0] | FB[1] | FB[2] | FB[3]) == 0;
+    // Copies of the slots' taps for frequency omega = a * dk into `dst`
+    // (64 dwords per slot: the entry's 2 NU dwords and what follows it).
+    auto copy_slots = [&](float2* dst, double a) {
+        const int js = index_of_slowness(a, A.b, A.nk, SL[wave * kSlots3 + (lane & (kSlots3 - 1))]);
+        for (int k = 0; k < nsl; ++k) {
+            const int j = __builtin_amdgcn_readlane(js, k);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rt, (lds_ptr_t)(dst + k * kSlotF2), 4, lane * 4,
+                                                     j * NU * (int)sizeof(float2), 0, 0);
+        }
+    };
+
     double img[kRows3];
 #pragma unroll
     for (int r = 0; r < kRows3; ++r) img[r] = 0.0;
-    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)A.tab, 0, A.nk * ((M + 1) * (M + 2) / 2) * (int)sizeof(float2), kRawBufferWord3);
     const int ny8 = A.ny * 8;
     // Byte offset of this lane's first output within a plane.  Rows at or
     // past nx land past the plane's end by themselves; a column past ny is
@@ -425,67 +551,95 @@ k_step3d(Step3dArgs A)
     // the vector-memory operations in flight (tile copies, output stores).
     typedef const __attribute__((address_space(4))) double* const_f64_ptr;
     const const_f64_ptr omc = (const_f64_ptr)A.omega;
-    double om = omc[wbeg];  // frequency of the coming iteration, loaded one ahead
-    for (int w = wbeg; w < wend; ++w) {
-        const int cur = (w - wbeg) & 1;
-        float2* Tb = T[cur];
-        // This wave's copies into Tb are complete; after the barrier so are
-        // every wave's, and nobody reads the other buffer any more.  After
-        // the first frequency, the copies were followed by the kRows3 output
-        // stores of the last pass (one per row, unconditional), which need
-        // not have completed.
-        if (w == wbeg)
-            wait_vmem_all();
-        else
-            wait_vmem_but_rows();
-        barrier_lds();
-        const double ar = om / A.dk;
-        if (w + 1 < wend) om = omc[w + 1];
-        int jrow[kRows3];
-#pragma unroll
-        for (int r = 0; r < kRows3; ++r)
-            jrow[r] = index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
-        // First taps of the first pass.  Vector-memory operations complete in
-        // issue order, so a tap load issued after the next tile's copy would
-        // wait for that copy: the copy is issued during the last pass instead,
-        // one tile row per row of that pass's first 2M rows (the rows of pair
-        // sums before its first output), and only tap reloads in the last
-        // pass's output rows can wait for it.
-        float2 h1[NC1];
-        int j1 = jrow[0];
-        load_pass_taps<M, 0, SPLIT>(h1, rt, j1);
-        const bool more = w + 1 < wend;
-        const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(A.in + (size_t)(more ? w + 1 : w) * plane), 0, pbytes, kRawBufferWord3);
-        float2* Tn = T[cur ^ 1];
-        auto copy_next = [&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int PRE = 2 * M > 0 ? 2 * M : 1;  // rows of the pass carrying the copy
-            constexpr int q0 = i < PRE ? i : QW;
-            constexpr int q1 = i + 1 < PRE ? (i + 1 < QW ? i + 1 : QW) : (i < PRE ? QW : 0);
-            if constexpr (q0 < q1) {
-                if (more) stage_rows<M, q0, q1>(Tn, rn, bias, x0, y0, A.ny, wave, lane);
-            }
-        };
-        auto no_copy = [](auto) {};
 
-        const float2* Tw = Tb + r0 * W + lane + M;  // tile row of x0 + r0 - M, column y
-        const __amdgpu_buffer_rsrc_t rq =
-            __builtin_amdgcn_make_buffer_rsrc((void*)(A.out + (size_t)w * plane), 0, pbytes,
-                                              kRawBufferWord3);
-        float2 acc[kRows3];
+    auto frequencies = [&](auto SLOTS_) {
+        constexpr bool SLOTS = decltype(SLOTS_)::value;
+        double om = omc[wbeg];  // frequency of the coming iteration, loaded one ahead
+        if constexpr (SLOTS) copy_slots(TS[0] + wave * kSlots3 * kSlotF2, om / A.dk);
+        for (int w = wbeg; w < wend; ++w) {
+            const int cur = (w - wbeg) & 1;
+            float2* Tb = T[cur];
+            // This wave's copies into Tb (and its slot copies) are complete;
+            // after the barrier so are every wave's, and nobody reads the other
+            // buffers any more.  After the first frequency, the copies were
+            // followed by the kRows3 output stores of the last pass (one per
+            // row, unconditional), which need not have completed.
+            if (w == wbeg)
+                wait_vmem_all();
+            else
+                wait_vmem_but_rows();
+            barrier_lds();
+            const double ar = om / A.dk;
+            if (w + 1 < wend) om = omc[w + 1];
+            // Row keys: slots, or table entries.
+            int keys[kRows3];
 #pragma unroll
-        for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
-        if constexpr (SPLIT <= M) {
-            fir_pass<M, 0, SPLIT, false>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8, no_copy);
-            float2 h2[NC2];
-            int j2 = -1;
-            fir_pass<M, SPLIT, M + 1, true>(Tw, jrow, h2, j2, rt, acc, img, rq, qbase, ny8,
-                                            copy_next);
-        } else {
-            fir_pass<M, 0, M + 1, true>(Tw, jrow, h1, j1, rt, acc, img, rq, qbase, ny8, copy_next);
+            for (int r = 0; r < kRows3; ++r)
+                keys[r] = SLOTS ? slot_of(slots, r)
+                                : index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
+            TapSrc ts;
+            ts.TSw = TS[cur] + wave * kSlots3 * kSlotF2;
+            ts.rt = rt;
+            // First taps of the first pass.  Vector-memory operations complete
+            // in issue order, so a tap load issued after the next tile's copy
+            // would wait for that copy: the copy is issued during the last pass
+            // instead, one tile row per row of that pass's first 2M rows (the
+            // rows of pair sums before its first output), and only tap loads
+            // in the last pass's output rows can wait for it (none with slots).
+            float2 h1[NC1];
+            int k1 = keys[0];
+            row_taps<M, 0, SPLIT, SLOTS>(h1, ts, k1);
+            const bool more = w + 1 < wend;
+            const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(A.in + (size_t)(more ? w + 1 : w) * plane), 0, pbytes, kRawBufferWord3);
+            float2* Tn = T[cur ^ 1];
+            // Column biases of the copy, formed again in the last pass (from a
+            // lane index the compiler cannot see through, so they are not kept
+            // in registers across the whole loop).
+            int biasn[stage_chunks<M>()];
+            auto copy_next = [&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (i == 0) {
+                    int ln = lane;
+                    __asm__ volatile("" : "+v"(ln));
+                    stage_bias<M>(biasn, y0, A.ny, ln);
+                    // the next frequency's slots (om was loaded one ahead)
+                    if constexpr (SLOTS)
+                        if (more) copy_slots(TS[cur ^ 1] + wave * kSlots3 * kSlotF2, om / A.dk);
+                }
+                constexpr int PRE = 2 * M > 0 ? 2 * M : 1;  // rows of the pass carrying the copy
+                constexpr int q0 = i < PRE ? i : QW;
+                constexpr int q1 = i + 1 < PRE ? (i + 1 < QW ? i + 1 : QW) : (i < PRE ? QW : 0);
+                if constexpr (q0 < q1) {
+                    if (more) stage_rows<M, q0, q1>(Tn, rn, biasn, x0, y0, A.ny, wave, lane);
+                }
+            };
+            auto no_copy = [](auto) {};
+
+            const float2* Tw = Tb + r0 * W + lane + M;  // tile row of x0 + r0 - M, column y
+            const __amdgpu_buffer_rsrc_t rq =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(A.out + (size_t)w * plane), 0, pbytes,
+                                                  kRawBufferWord3);
+            float2 acc[kRows3];
+#pragma unroll
+            for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
+            if constexpr (SPLIT <= M) {
+                fir_pass<M, 0, SPLIT, false, true, SLOTS>(Tw, ts, keys, h1, k1, acc, img, rq, qbase,
+                                                          ny8, no_copy);
+                float2 h2[NC2];
+                int k2 = -1;
+                fir_pass<M, SPLIT, M + 1, true, false, SLOTS>(Tw, ts, keys, h2, k2, acc, img, rq,
+                                                              qbase, ny8, copy_next);
+            } else {
+                fir_pass<M, 0, M + 1, true, true, SLOTS>(Tw, ts, keys, h1, k1, acc, img, rq, qbase,
+                                                         ny8, copy_next);
+            }
         }
-    }
+    };
+    if (use_slots)
+        frequencies(std::true_type{});
+    else
+        frequencies(std::false_type{});
 
 #pragma unroll
     for (int r = 0; r < kRows3; ++r) {
