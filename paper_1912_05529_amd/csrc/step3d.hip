@@ -164,18 +164,36 @@ __device__ __forceinline__ void load_pass_taps(float2 (&h)[pass_slot(M, LO, HI, 
     });
 }
 
+typedef float v2f3 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(3))) v2f3* lds_cf2;
+
+__device__ __forceinline__ float2 lds_c64(lds_cf2 p)
+{
+    const v2f3 v = *p;
+    return make_float2(v.x, v.y);
+}
+
+// An LDS address the compiler cannot split into a constant and a variable
+// part: reads from it then put their small offsets in the instructions'
+// offset fields instead of one address add per read.
+__device__ __forceinline__ lds_cf2 opaque_lds(const float2* p)
+{
+    const unsigned a = (unsigned)(size_t)(const __attribute__((address_space(3))) void*)p;
+    return (lds_cf2)(size_t)(unsigned)__builtin_amdgcn_readfirstlane((int)a);
+}
+
 // The same taps from an LDS slot holding the NU unique coefficients of one
 // table entry (in coefficient order).
 template <int M, int LO, int HI>
 __device__ __forceinline__ void lds_pass_taps(float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)],
-                                              const float2* slot)
+                                              lds_cf2 slot)
 {
     static_for<0, M + 1>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
         static_for<0, a + 1>([&](auto BB) {
             constexpr int b = decltype(BB)::value;
             if constexpr (in_set(a, LO, HI) || in_set(b, LO, HI))
-                h[pass_slot(M, LO, HI, a, b)] = slot[cidx(a, b)];
+                h[pass_slot(M, LO, HI, a, b)] = lds_c64(slot + cidx(a, b));
         });
     });
 }
@@ -190,7 +208,7 @@ __device__ __forceinline__ int slot_of(unsigned slots, int r) { return (slots >>
 // may or may not have been issued are conservative and would also wait for
 // the tile copy in flight.
 struct TapSrc {
-    const float2* TSw;
+    lds_cf2 TSw;
     __amdgpu_buffer_rsrc_t rt;
 };
 
@@ -217,13 +235,17 @@ struct Acc3 {
 // `issue(i)` runs at the start of row i of the pass (the last pass uses it
 // to copy the next frequency's tile a few rows at a time).
 // Taps are reloaded at a row where some lane's key (slot or table entry,
-// keys[r]) differs from the one its registers hold (kcur).
-template <int M, int LO, int HI, bool LAST, bool PRELOADED, bool SLOTS, typename Issue>
+// keys[r]) differs from the one its registers hold (kcur).  With LDS_TAPS
+// (slots only) no taps are held: each output row reads its slot's taps from
+// LDS as it multiplies, which frees the registers of a tap set, enough for one
+// pass over all planes (no split, so the unique multiply-adds only).
+template <int M, int LO, int HI, bool LAST, bool PRELOADED, bool SLOTS, bool LDS_TAPS,
+          typename Issue>
 __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const TapSrc& ts,
                                          const int (&keys)[kRows3],
                                          float2 (&h)[pass_slot(M, LO, HI, M + 1, 0)], int& kcur,
                                          float2 (&acc)[kRows3], double (&img)[kRows3],
-                                         __amdgpu_buffer_rsrc_t rq, int qbase, int ny8,
+                                         __amdgpu_buffer_rsrc_t rq, int qbase, int ny8, int Wr,
                                          Issue&& issue)
 {
     constexpr int W = kLanes3 + 2 * M;
@@ -236,18 +258,23 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const Ta
     float2 v[2][2 * NP];
     auto fetch = [&](auto I) {
         constexpr int i = decltype(I)::value;
-        const float2* row = Tw + i * W;
+        // The row stride is a run-time value (Wr == W): one register then
+        // holds the row's first column (y - M) and the reads take their
+        // columns from the instructions' small offset fields, instead of an
+        // address add per read pair (paired reads reach only 255 values past
+        // their base).
+        const float2* row = Tw + i * Wr - M;
         static_for<0, NP>([&](auto Q) {
             constexpr int q = decltype(Q)::value;
             constexpr int b = LO + q;
-            v[i & 1][2 * q] = row[b];
-            if constexpr (b != 0) v[i & 1][2 * q + 1] = row[-b];
+            v[i & 1][2 * q] = row[M + b];
+            if constexpr (b != 0) v[i & 1][2 * q + 1] = row[M - b];
         });
     };
     // Taps of the first output row (unless the caller has them), requested
     // before the 2M rows of pair sums that precede it, so their latency hides
     // behind those rows.
-    if constexpr (!PRELOADED) {
+    if constexpr (!PRELOADED && !LDS_TAPS) {
         row_taps<M, LO, HI, SLOTS>(h, ts, keys[0]);
         kcur = keys[0];
     }
@@ -270,10 +297,13 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const Ta
         if constexpr (i >= 2 * M) {
             constexpr int r = i - 2 * M;  // output row x0 + r0 + r
             constexpr int c = r + M;      // its pair sums
-            if (__builtin_amdgcn_ballot_w64(keys[r] != kcur) != 0) {
-                row_taps<M, LO, HI, SLOTS>(h, ts, keys[r]);
-                kcur = keys[r];
+            if constexpr (!LDS_TAPS) {
+                if (__builtin_amdgcn_ballot_w64(keys[r] != kcur) != 0) {
+                    row_taps<M, LO, HI, SLOTS>(h, ts, keys[r]);
+                    kcur = keys[r];
+                }
             }
+            const lds_cf2 tp = ts.TSw + (LDS_TAPS ? keys[r] : 0) * kSlotF2;
             Acc3 o{acc[r].x, 0.0f, acc[r].y};
             static_for<0, M + 1>([&](auto AA) {
                 constexpr int a = decltype(AA)::value;
@@ -303,10 +333,15 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const Ta
                             else
                                 sum = c_add(Y[c + a][b - LO], Y[c - a][b - LO]);
                         }
-                        o.re1 = fmaf(h[n].x, sum.x, o.re1);
-                        o.re2 = fmaf(h[n].y, sum.y, o.re2);
-                        o.im = fmaf(h[n].x, sum.y, o.im);
-                        o.im = fmaf(h[n].y, sum.x, o.im);
+                        float2 hv;
+                        if constexpr (LDS_TAPS)
+                            hv = lds_c64(tp + cidx(a, b));
+                        else
+                            hv = h[n];
+                        o.re1 = fmaf(hv.x, sum.x, o.re1);
+                        o.re2 = fmaf(hv.y, sum.y, o.re2);
+                        o.im = fmaf(hv.x, sum.y, o.im);
+                        o.im = fmaf(hv.y, sum.x, o.im);
                     }
                 });
             });
@@ -389,15 +424,17 @@ k_step3d(Step3dArgs A)
     constexpr int NC2 = pass_slot(M, SPLIT, M + 1, M + 1, 0);
     constexpr int QW = HP / kWaves3;       // tile rows copied by each wave
     // LDS in one block, in this order: the targets of buffer-to-LDS copies
-    // (tap slots, tiles) come first and stay within the low 64 KiB.
+    // (tiles, tap slots) come first and stay within the low 64 KiB; the tiles
+    // start at address 0, so a row address plus a column offset fits the
+    // offset field of the paired reads.
     struct Lds {
-        float2 TS[2][kWaves3 * kSlots3 * kSlotF2];  // tap slots, by frequency parity
         float2 T[2][HP * W];                        // double-buffered frequency tiles
+        float2 TS[2][kWaves3 * kSlots3 * kSlotF2];  // tap slots, by frequency parity
         double S[kTileX3 * kLanes3];                // slowness of the tile
         double SL[kWaves3 * kSlots3];               // slowness of each slot
         int FB[kWaves3];                            // wave has points without a slot
     };
-    static_assert(offsetof(Lds, S) <= 65536, "copy targets below 64 KiB");
+    static_assert(offsetof(Lds, S) <= 65536 && offsetof(Lds, T) == 0, "copy targets below 64 KiB");
     __shared__ Lds L;
     auto& TS = L.TS;
     auto& T = L.T;
@@ -541,6 +578,7 @@ k_step3d(Step3dArgs A)
 #pragma unroll
     for (int r = 0; r < kRows3; ++r) img[r] = 0.0;
     const int ny8 = A.ny * 8;
+    const int Wr = __builtin_amdgcn_readfirstlane(A.nx > 0 ? W : W + 1);  // == W
     // Byte offset of this lane's first output within a plane.  Rows at or
     // past nx land past the plane's end by themselves; a column past ny is
     // moved out of range as a whole (stores out of range are dropped).
@@ -578,7 +616,7 @@ k_step3d(Step3dArgs A)
                 keys[r] = SLOTS ? slot_of(slots, r)
                                 : index_of_slowness(ar, A.b, A.nk, S[(r0 + r) * kLanes3 + lane]);
             TapSrc ts;
-            ts.TSw = TS[cur] + wave * kSlots3 * kSlotF2;
+            ts.TSw = opaque_lds(TS[cur] + wave * kSlots3 * kSlotF2);
             ts.rt = rt;
             // First taps of the first pass.  Vector-memory operations complete
             // in issue order, so a tap load issued after the next tile's copy
@@ -588,7 +626,7 @@ k_step3d(Step3dArgs A)
             // in the last pass's output rows can wait for it (none with slots).
             float2 h1[NC1];
             int k1 = keys[0];
-            row_taps<M, 0, SPLIT, SLOTS>(h1, ts, k1);
+            if constexpr (!SLOTS) row_taps<M, 0, SPLIT, SLOTS>(h1, ts, k1);
             const bool more = w + 1 < wend;
             const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)(A.in + (size_t)(more ? w + 1 : w) * plane), 0, pbytes, kRawBufferWord3);
@@ -623,16 +661,22 @@ k_step3d(Step3dArgs A)
             float2 acc[kRows3];
 #pragma unroll
             for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
-            if constexpr (SPLIT <= M) {
-                fir_pass<M, 0, SPLIT, false, true, SLOTS>(Tw, ts, keys, h1, k1, acc, img, rq, qbase,
-                                                          ny8, no_copy);
+            if constexpr (SLOTS) {
+                float2 hu[NU];  // unused: taps come from LDS
+                int ku = 0;
+                fir_pass<M, 0, M + 1, true, true, true, true>(Tw, ts, keys, hu, ku, acc, img, rq,
+                                                              qbase, ny8, Wr, copy_next);
+            } else if constexpr (SPLIT <= M) {
+                fir_pass<M, 0, SPLIT, false, true, false, false>(Tw, ts, keys, h1, k1, acc, img,
+                                                                 rq, qbase, ny8, Wr, no_copy);
                 float2 h2[NC2];
                 int k2 = -1;
-                fir_pass<M, SPLIT, M + 1, true, false, SLOTS>(Tw, ts, keys, h2, k2, acc, img, rq,
-                                                              qbase, ny8, copy_next);
+                fir_pass<M, SPLIT, M + 1, true, false, false, false>(Tw, ts, keys, h2, k2, acc,
+                                                                     img, rq, qbase, ny8, Wr,
+                                                                     copy_next);
             } else {
-                fir_pass<M, 0, M + 1, true, true, SLOTS>(Tw, ts, keys, h1, k1, acc, img, rq, qbase,
-                                                         ny8, copy_next);
+                fir_pass<M, 0, M + 1, true, true, false, false>(Tw, ts, keys, h1, k1, acc, img, rq,
+                                                                qbase, ny8, Wr, copy_next);
             }
         }
     };
