@@ -555,6 +555,8 @@ k_step3d(Step3dArgs A)
             nsl = k + 1;
         }
     }
+    // Whether all the wave's points share slot 0 (then nothing is reloaded).
+    const bool one_slot = nsl == 1;
     // One path per workgroup: slots when every point of every wave has one.
     bool none = false;
 #pragma unroll
@@ -662,10 +664,33 @@ k_step3d(Step3dArgs A)
 #pragma unroll
             for (int r = 0; r < kRows3; ++r) acc[r] = make_float2(0.0f, 0.0f);
             if constexpr (SLOTS) {
-                float2 hu[NU];  // unused: taps come from LDS
-                int ku = 0;
-                fir_pass<M, 0, M + 1, true, true, true, true>(Tw, ts, keys, hu, ku, acc, img, rq,
-                                                              qbase, ny8, Wr, copy_next);
+                // A wave whose points all share one slot keeps its taps in
+                // registers (loaded once per pass, no reload), and takes the
+                // plane split; the others read taps from LDS row by row in one
+                // pass.  Passes hold no barrier, so waves may differ.
+                auto lds_pass = [&]() {
+                    float2 hu[NU];  // unused: taps come from LDS
+                    int ku = 0;
+                    fir_pass<M, 0, M + 1, true, true, true, true>(Tw, ts, keys, hu, ku, acc, img,
+                                                                  rq, qbase, ny8, Wr, copy_next);
+                };
+                if constexpr (SPLIT <= M) {
+                    if (one_slot) {
+                        row_taps<M, 0, SPLIT, true>(h1, ts, k1);
+                        fir_pass<M, 0, SPLIT, false, true, true, false>(Tw, ts, keys, h1, k1, acc,
+                                                                        img, rq, qbase, ny8, Wr,
+                                                                        no_copy);
+                        float2 h2[NC2];
+                        int k2 = -1;
+                        fir_pass<M, SPLIT, M + 1, true, false, true, false>(Tw, ts, keys, h2, k2,
+                                                                            acc, img, rq, qbase,
+                                                                            ny8, Wr, copy_next);
+                    } else {
+                        lds_pass();
+                    }
+                } else {
+                    lds_pass();
+                }
             } else if constexpr (SPLIT <= M) {
                 fir_pass<M, 0, SPLIT, false, true, false, false>(Tw, ts, keys, h1, k1, acc, img,
                                                                  rq, qbase, ny8, Wr, no_copy);
