@@ -298,14 +298,19 @@ int launch_reg(const AdjArgs& a, size_t lds, hipStream_t s)
 // forward step costs.  Change points are those of the slowness (a velocity
 // change that keeps the entry adds exact zeros).
 //
-// Mapping: as the forward register-tap kernel (two outputs per thread, two
-// alternating tap sets, plane ping-pong in LDS, one barrier per step).  A
-// wave owns 128 consecutive outputs and adds the corrections of its own
-// outputs: the triangle of a change point is cut into at most 64 chunks of
-// at most T terms (a fixed table, one chunk per lane), each lane sums its
-// chunk and adds it to the output in LDS after the owner's store, in the
-// same wave, so no extra barrier is needed; the chunks of one output are
-// added one rank after another, so the result is run-to-run identical.
+// Mapping: as the forward register-tap kernel (two outputs per thread, plane
+// ping-pong in LDS, one barrier per step), with one tap set per output,
+// refilled at the end of a step where the row changes.  A wave owns 128
+// consecutive outputs and computes the corrections of its own outputs at the
+// start of a step: the triangle of a change point is cut into at most 64
+// chunks of at most T terms (a fixed table, one chunk per lane, the chunks of
+// one output in consecutive lanes); each lane sums its chunk, the chunk sums
+// of an output are added at its first chunk's lane (DPP lane shifts) and that
+// lane adds the total to the wave's correction row in LDS; each lane adds its
+// two entries of the row to its FIR results and clears them.  All of it stays
+// within the wave (LDS keeps one wave's accesses in order), so no extra
+// barrier is needed, and every sum is formed in a fixed order, so the result
+// is run-to-run identical.
 // The differences D_c of the next step are built during a step: the entry
 // pairs (from the change-point pre-pass) are loaded two steps ahead, the two
 // table rows one step ahead, and the differences go to an LDS cache before
@@ -414,40 +419,80 @@ __device__ __forceinline__ void fold2(const float2* __restrict__ win, const floa
     o1 = a1;
 }
 
-// LDS of the folded kernel: two planes, then per parity the differences
-// D_c[1..M], the change count and the positions.
+// LDS of the folded kernel: two planes, a row of corrections per wave (its
+// 128 outputs), then per parity the differences D_c[1..M] of each change
+// point followed by a zero.
 __host__ __device__ constexpr int fold_plane_len(int tsub, int M) { return 2 * tsub + 2 * M + 2; }
+__host__ __device__ constexpr int fold_lds_len(int tsub, int M)
+{
+    return 2 * fold_plane_len(tsub, M) + 2 * tsub + 2 * kAdjKmax * (M + 1);
+}
 __host__ __device__ constexpr size_t fold_lds(int tsub, int M)
 {
-    return (size_t)2 * fold_plane_len(tsub, M) * sizeof(float2) +
-           (size_t)2 * kAdjKmax * M * sizeof(float2) + (size_t)2 * (kAdjKmax + 1) * sizeof(int);
+    return (size_t)fold_lds_len(tsub, M) * sizeof(float2);
 }
 
-// A lane's chunk, packed: side (bit 0), d (bits 1-6), e0 (7-12), len (13-18),
-// rank (19-21).
-__device__ __forceinline__ int pack_chunk(const AdjChunk& c)
+// A lane's part in the correction of a change point c: its chunk's terms read
+// the differences D_c[1 + dofs[e]] (index M is the zero after them) and the
+// values q[c + qofs[e]]; `info` packs side (bit 0), d (bits 1-6), whether the
+// lane leads its output's chunks (bit 7) and how many chunks that output has
+// (bits 8-15).
+template <int T>
+struct FoldLane {
+    int dofs[T], qofs[T];
+    int info;
+};
+
+template <int M, int T>
+__device__ FoldLane<T> fold_lane(int lane)
 {
-    return c.side | (c.d << 1) | (c.e0 << 7) | (c.len << 13) | (c.rank << 19);
+    const AdjChunk c = adj_lane_chunk(lane, M, T);
+    FoldLane<T> L;
+    const int terms = c.side ? M - c.d : M - c.d + 1;
+    const int nr = (terms + T - 1) / T;
+    const int d0 = (c.side ? c.d : c.d - 1) + c.e0;
+#pragma unroll
+    for (int e = 0; e < T; ++e) {
+        const bool in = e < c.len;
+        L.dofs[e] = in ? d0 + e : M;
+        L.qofs[e] = in ? (c.side ? -(1 + c.e0 + e) : c.e0 + e) : 0;
+    }
+    L.info = c.side | (c.d << 1) | ((c.len > 0 && c.rank == 0) << 7) | (nr << 8);
+    return L;
+}
+
+// v of lane l + 1 at lane l (0 at the last lane): a DPP wave shift
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
 struct FoldState {
-    int t, x0, lane, xw, LB, chunk;
+    int t, x0, lane, xw, LB;
     bool ok0, ok1;
     int c0, c1;        // image columns (clamped into the section)
     double ar;
     // loader: thread t builds D_c[m] of change point i, t = i*M + m-1
     bool on;
-    int jp;            // (left | right << 16) entries of change point i, next row
-    int pos, pos_cur;  // its position (next row, the row being built)
-    int cnt;           // change count of the next row (loaded a step ahead)
     int i_ld, m_ld;    // loader role: change point i_ld, tap m_ld
-    float2 hl, hr;     // table taps in flight
+};
+
+// What a step hands to the next one, formed after its FIR from values it
+// loaded at its start: nothing a step starts with waits for a load (a load
+// completes in order, so a wait at the start of a step would also wait for
+// the tap refills issued at the end of the step before).
+struct FoldCarry {
+    unsigned long long mask;  // the row's change points that reach the wave's outputs (uniform)
+    int mp;                   // their positions (lane i: the i-th)
+    int nb;                   // change count of the row after (uniform)
+    int jp;                   // (left | right << 16) entries of its change point i_ld
+    double2 img;              // image row
 };
 
 template <int M>
-__device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* dh, int* cc, int* cp,
-                                          FoldState& F, int k_in, float2 (&h)[2][M + 1],
-                                          double2& sn, double2& img)
+__device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float4* cw, float2* dh,
+                                          const FoldState& F, const FoldLane<adj_chunk_len(M)>& CL,
+                                          int k_in, float2 (&h)[2][M + 1], FoldCarry& C)
 {
     constexpr int T = adj_chunk_len(M);
     constexpr int R = (M + T - 1) / T;
@@ -455,78 +500,44 @@ __device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* 
     // address computation on the scalar unit
     const int k = __builtin_amdgcn_readfirstlane(k_in);
     const int nx = a.nx;
-    const double2 cimg = img;
-    // change points of row k (cache k&1, complete since the last barrier)
-    // that reach this wave's outputs: read before the FIR so that their LDS
-    // latency overlaps it
-    const int n_cur = cc[k & 1];
-    const int mypos = F.lane < n_cur ? cp[(k & 1) * kAdjKmax + F.lane] : 0;
-    const bool rel = F.lane < n_cur && mypos >= F.xw - M + 1 && mypos <= F.xw + 127 + M;
-    // row k-1's change count, loaded a step ago (uniform)
-    const int cnt = __builtin_amdgcn_readfirstlane(F.cnt);
-    const int n_build = cnt < a.kmax ? cnt : a.kmax;
+    const double2 cimg = C.img;
+    // change points of row k that reach this wave's outputs, and row k-1's
+    // change count (both formed during the step before)
+    const unsigned long long mask0 = C.mask;
+    const int mypos = C.mp;
+    const int n_build = C.nb;
     const int i_ld = F.i_ld, m_ld = F.m_ld;
     const bool build = k >= 1 && F.on && i_ld < n_build;
-    // loader: table rows of row k-1's change points (entries loaded a step ago)
-    if (build) {
-        F.hr = load_global(a.tab + (size_t)((unsigned)F.jp >> 16) * (M + 1) + m_ld);
-        F.hl = load_global(a.tab + (size_t)((unsigned)F.jp & 0xffffu) * (M + 1) + m_ld);
-    }
-    F.pos_cur = F.pos;
-    // prefetches for the next steps, branch-free (rows clamped; values past
-    // the top are unused): slowness row k-1 (flagged where it differs from
-    // row k) for the refill at the end of this step, image row k-1, and the
-    // change points of row k-2 for the next step's loader
-    {
-        const int ks = k >= 1 ? k - 1 : 0, kn = k >= 2 ? k - 2 : 0;
-        sn = load_global(reinterpret_cast<const double2*>(a.slow + (size_t)ks * a.ldp + F.x0));
-        img = make_double2(a.image[(size_t)ks * nx + F.c0], a.image[(size_t)ks * nx + F.c1]);
-        // a vector load: as a scalar load its completion would be tracked by
-        // the counter the FIR's LDS waits use, and they would wait for it
-        int zero = 0;
-        asm volatile("" : "+v"(zero));
-        F.cnt = *as_global(&a.chg[kn].cnt + zero);
-        const int il = F.on ? i_ld : 0;
-        F.pos = *as_global(&a.chg[kn].pos[il]);
-        F.jp = *as_global(a.jpair + ((size_t)kn * a.nw + blockIdx.x) * kAdjKmax + il);
-    }
-    // own-filter FIR on Q_{k+1} (plane (k+1)&1), plus the image row
     const int LB = F.LB;
     const float2* Pin = sm + ((k + 1) & 1) * LB;
     float2* Pout = sm + (k & 1) * LB + M;
-    float2 o0, o1;
-    fold2<M>(Pin + F.x0, h[0], h[1], o0, o1);
-    o0.x += (float)cimg.x;
-    o1.x += (float)cimg.y;
-    if (F.ok0) Pout[F.x0] = o0;
-    if (F.ok1) Pout[F.x0 + 1] = o1;
-    // corrections of this wave's outputs around the change points of row k:
-    // per change point every lane reads its chunk's T differences and window
-    // values at once (addresses clamped into the arrays, terms past the
-    // chunk multiplied by zero), then adds the sum after the owner's store
-    {
-        unsigned long long mask = __ballot(rel);
-        const float2* dk = dh + (k & 1) * kAdjKmax * M;
-        const int side = F.chunk & 1, d = (F.chunk >> 1) & 63, e0 = (F.chunk >> 7) & 63;
-        const int len = (F.chunk >> 13) & 63, rank = (F.chunk >> 19) & 7;
-        const int qs = side ? -1 : 1;
-        const int doff = (side ? d : d - 1) + e0;   // first difference index (m - 1)
+    float4* cwv = cw + (F.t >> 6) * 64;  // this wave's outputs, by pair
+    // corrections of this wave's outputs around the change points of row k
+    // (Q_{k+1} is complete since the barrier): per change point every lane
+    // sums its chunk's T terms (terms past the chunk read the zero after the
+    // differences), the chunks of one output (in consecutive lanes) are added
+    // at its leading lane and that sum goes to the wave's correction row,
+    // change points in increasing order.  They come first in the step, even
+    // before the loads are issued, so that their LDS reads go ahead of the
+    // other waves' FIR window reads: a wave with corrections is the step's
+    // slowest, and behind those reads its own waited for most of a step.
+    if (mask0) {
+        const float2* dk = dh + (k & 1) * kAdjKmax * (M + 1);
+        float* cwf = reinterpret_cast<float*>(cwv);
+        const int side = CL.info & 1, d = (CL.info >> 1) & 63, lead = (CL.info >> 7) & 1;
+        const int nr = CL.info >> 8;
+        unsigned long long mask = mask0;
         while (mask) {
             const int i = __builtin_ctzll(mask);
             mask &= mask - 1;
             const int c = __builtin_amdgcn_readlane(mypos, i);
-            const int x = side ? c + d : c - d;
-            const bool act = len > 0 && x >= F.xw && x < F.xw + 128 && x >= 0 && x < nx;
-            const int q0 = M + (side ? c - 1 - e0 : c + e0);
-            // terms past the chunk read Pin[0], a zero of the plane's halo
+            const float2* qb = Pin + M + c;
+            const float2* db = dk + i * (M + 1);
             float2 hd[T], qv[T];
 #pragma unroll
             for (int e = 0; e < T; ++e) {
-                int di = doff + e;
-                di = di < 0 ? 0 : (di > M - 1 ? M - 1 : di);
-                const int qi = e < len ? q0 + e * qs : 0;
-                hd[e] = dk[i * M + di];
-                qv[e] = Pin[qi];
+                hd[e] = db[CL.dofs[e]];
+                qv[e] = qb[CL.qofs[e]];
             }
             float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
@@ -536,23 +547,85 @@ __device__ __forceinline__ void fold_step(const AdjArgs& a, float2* sm, float2* 
                 acc.y = fmaf(hd[e].x, qv[e].y, acc.y);
                 acc.y = fmaf(-hd[e].y, qv[e].x, acc.y);
             }
-            if (side) acc = make_float2(-acc.x, -acc.y);
+            float2 tot = acc, s = acc;
 #pragma unroll
-            for (int q = 0; q < R; ++q)
-                if (act && rank == q) {
-                    __hip_atomic_fetch_add(&Pout[x].x, acc.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_fetch_add(&Pout[x].y, acc.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int q = 1; q < R; ++q) {
+                s = make_float2(lane_next(s.x), lane_next(s.y));
+                if (nr > q) {
+                    tot.x += s.x;
+                    tot.y += s.y;
                 }
+            }
+            if (side) tot = make_float2(-tot.x, -tot.y);
+            const int xi = (side ? c + d : c - d) - F.xw;
+            if (lead && xi >= 0 && xi < 128) {
+                __hip_atomic_fetch_add(cwf + 2 * xi, tot.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                __hip_atomic_fetch_add(cwf + 2 * xi + 1, tot.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
         }
+    }
+    // loader: table rows of row k-1's change points
+    float2 hr = make_float2(0.0f, 0.0f), hl = hr;
+    if (build) {
+        hr = load_global(a.tab + (size_t)((unsigned)C.jp >> 16) * (M + 1) + m_ld);
+        hl = load_global(a.tab + (size_t)((unsigned)C.jp & 0xffffu) * (M + 1) + m_ld);
+    }
+    // loads for this step's end and the next step, branch-free (rows clamped;
+    // values past the top are unused): slowness row k-1 (flagged where it
+    // differs from row k) for the refill at the end of this step, image row
+    // k-1 and its change points, the change count and entries of row k-2
+    double2 sn, img_n;
+    int cnt_n, mp_n, jp_n;
+    {
+        const int ks = k >= 1 ? k - 1 : 0, kn = k >= 2 ? k - 2 : 0;
+        sn = load_global(reinterpret_cast<const double2*>(a.slow + (size_t)ks * a.ldp + F.x0));
+        img_n = make_double2(a.image[(size_t)ks * nx + F.c0], a.image[(size_t)ks * nx + F.c1]);
+        // vector loads: as scalar loads their completion would be tracked by
+        // the counter the FIR's LDS waits use, and they would wait for them
+        int zero = 0;
+        asm volatile("" : "+v"(zero));
+        cnt_n = *as_global(&a.chg[kn].cnt + zero);
+        mp_n = *as_global(&a.chg[ks].pos[F.lane < kAdjKmax ? F.lane : 0]);
+        const int il = F.on ? i_ld : 0;
+        jp_n = *as_global(a.jpair + ((size_t)kn * a.nw + blockIdx.x) * kAdjKmax + il);
+    }
+    // own-filter FIR on Q_{k+1} (plane (k+1)&1), plus the image row and the
+    // corrections (read back and cleared: LDS keeps one wave's accesses in
+    // order, the fence keeps the compiler from moving the read up)
+    float2 o0, o1;
+    fold2<M>(Pin + F.x0, h[0], h[1], o0, o1);
+    o0.x += (float)cimg.x;
+    o1.x += (float)cimg.y;
+    if (mask0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const float4 c4 = cwv[F.lane];
+        o0.x += c4.x;
+        o0.y += c4.y;
+        o1.x += c4.z;
+        o1.y += c4.w;
+        cwv[F.lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    if (F.ok0) Pout[F.x0] = o0;
+    if (F.ok1) Pout[F.x0 + 1] = o1;
+    // the next step's values, formed here (the loads have had the FIR's time);
+    // the empty asm statements make each value exist at this point
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        const bool rel = F.lane < n_build && mp_n >= F.xw - M + 1 && mp_n <= F.xw + 127 + M;
+        C.mask = __ballot(rel);
+        const int c = __builtin_amdgcn_readfirstlane(cnt_n);
+        C.nb = c < a.kmax ? c : a.kmax;
+        asm volatile("" : "+v"(mp_n), "+v"(jp_n), "+v"(img_n.x), "+v"(img_n.y));
+        C.mp = mp_n;
+        C.jp = jp_n;
+        C.img = img_n;
     }
     if (k >= 1) {
         // differences of row k-1 into the other cache (read from step k-1 on)
-        const int kp = (k - 1) & 1;
         if (build) {
-            dh[(kp * kAdjKmax + i_ld) * M + m_ld - 1] = make_float2(F.hr.x - F.hl.x, F.hr.y - F.hl.y);
-            if (m_ld == 1) cp[kp * kAdjKmax + i_ld] = F.pos_cur;
+            const int kp = (k - 1) & 1;
+            dh[(kp * kAdjKmax + i_ld) * (M + 1) + m_ld - 1] = make_float2(hr.x - hl.x, hr.y - hl.y);
         }
-        if (F.t == 0) cc[kp] = n_build;
         // taps of step k-1 where row k-1 differs from row k; the FIR of the
         // next step waits for them (mostly L1 hits: the rows of one frequency)
         if (slowness_changed(sn.x))
@@ -573,9 +646,8 @@ __global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
     FoldState F;
     F.LB = fold_plane_len(tsub, M);
     float2* sm = reinterpret_cast<float2*>(smem4);
-    float2* dh = sm + 2 * F.LB;                                    // [2][kAdjKmax][M]
-    int* cc = reinterpret_cast<int*>(dh + 2 * kAdjKmax * M);       // [2]
-    int* cp = cc + 2;                                              // [2][kAdjKmax]
+    float4* cw = reinterpret_cast<float4*>(sm + 2 * F.LB);         // [tsub] (a pair per thread)
+    float2* dh = sm + 2 * F.LB + 2 * tsub;                          // [2][kAdjKmax][M+1]
     F.t = threadIdx.x;
     F.x0 = 2 * F.t;
     F.lane = F.t & 63;
@@ -585,13 +657,13 @@ __global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
     F.c0 = F.ok0 ? F.x0 : 0;
     F.c1 = F.ok1 ? F.x0 + 1 : 0;
     F.ar = a.omega[r] / a.dk;
-    F.chunk = pack_chunk(adj_lane_chunk(F.lane, M, T));
+    const FoldLane<T> CL = fold_lane<M, T>(F.lane);
     const int i_ld = F.t / M, m_ld = F.t - i_ld * M + 1;
     F.i_ld = i_ld;
     F.m_ld = m_ld;
     F.on = i_ld < a.kmax;
 
-    for (int i = F.t; i < 2 * F.LB; i += tsub) sm[i] = make_float2(0.0f, 0.0f);
+    for (int i = F.t; i < fold_lds_len(tsub, M); i += tsub) sm[i] = make_float2(0.0f, 0.0f);
     __syncthreads();
     // Q_{nz-1} = image row nz-1, in plane (nz-1)&1
     {
@@ -600,8 +672,10 @@ __global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
         if (F.ok1) P[F.x0 + 1] = make_float2((float)a.image[(size_t)(nz - 1) * nx + F.x0 + 1], 0.0f);
     }
     // prologue: differences of the first step (row nz-2) into cache
-    // (nz-2)&1; entries of row nz-3 loaded for the first step's loader
+    // (nz-2)&1, its change points for the corrections; entries of row nz-3
+    // loaded for the first step's loader
     int k = nz - 2;
+    FoldCarry C;
     {
         const int c = a.chg[k].cnt;
         const int n = c < a.kmax ? c : a.kmax;
@@ -609,16 +683,14 @@ __global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
             const int jp = a.jpair[((size_t)k * a.nw + r) * kAdjKmax + i_ld];
             const float2 hr = a.tab[(size_t)((unsigned)jp >> 16) * (M + 1) + m_ld];
             const float2 hl = a.tab[(size_t)((unsigned)jp & 0xffffu) * (M + 1) + m_ld];
-            dh[((k & 1) * kAdjKmax + i_ld) * M + m_ld - 1] = make_float2(hr.x - hl.x, hr.y - hl.y);
-            if (m_ld == 1) cp[(k & 1) * kAdjKmax + i_ld] = a.chg[k].pos[i_ld];
+            dh[((k & 1) * kAdjKmax + i_ld) * (M + 1) + m_ld - 1] = make_float2(hr.x - hl.x, hr.y - hl.y);
         }
-        if (F.t == 0) cc[k & 1] = n;
+        C.mp = a.chg[k].pos[F.lane < kAdjKmax ? F.lane : 0];
+        C.mask = __ballot(F.lane < n && C.mp >= F.xw - M + 1 && C.mp <= F.xw + 127 + M);
         const int kn = k >= 1 ? k - 1 : k;
-        F.cnt = a.chg[kn].cnt;
-        F.pos = F.on ? a.chg[kn].pos[i_ld] : 0;
-        F.jp = F.on ? a.jpair[((size_t)kn * a.nw + r) * kAdjKmax + i_ld] : 0;
-        F.pos_cur = 0;
-        F.hl = F.hr = make_float2(0.0f, 0.0f);
+        const int cn = a.chg[kn].cnt;
+        C.nb = cn < a.kmax ? cn : a.kmax;
+        C.jp = F.on ? a.jpair[((size_t)kn * a.nw + r) * kAdjKmax + i_ld] : 0;
     }
     // taps of the first step (row nz-2)
     float2 h[2][M + 1];
@@ -627,11 +699,10 @@ __global__ void __launch_bounds__(512) k_demigrate_fold(AdjArgs a)
         load_taps_adj<M>(h[0], a.tab + (size_t)index_of_slowness(F.ar, a.b, a.nk, slowness_value(s0.x)) * (M + 1));
         load_taps_adj<M>(h[1], a.tab + (size_t)index_of_slowness(F.ar, a.b, a.nk, slowness_value(s0.y)) * (M + 1));
     }
-    double2 sn = make_double2(0.0, 0.0);
-    double2 img = make_double2(a.image[(size_t)k * nx + F.c0], a.image[(size_t)k * nx + F.c1]);
+    C.img = make_double2(a.image[(size_t)k * nx + F.c0], a.image[(size_t)k * nx + F.c1]);
     __syncthreads();
 
-    for (; k >= 0; --k) fold_step<M>(a, sm, dh, cc, cp, F, k, h, sn, img);
+    for (; k >= 0; --k) fold_step<M>(a, sm, cw, dh, F, CL, k, h, C);
     const float2* P0 = sm + M;  // Q_0 is in plane 0
     if (F.ok0) a.out[(size_t)F.x0 * a.nw + r] = P0[F.x0];
     if (F.ok1) a.out[(size_t)(F.x0 + 1) * a.nw + r] = P0[F.x0 + 1];

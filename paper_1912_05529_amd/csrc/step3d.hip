@@ -248,7 +248,6 @@ __device__ __forceinline__ void fir_pass(const float2* __restrict__ Tw, const Ta
                                          __amdgpu_buffer_rsrc_t rq, int qbase, int ny8, int Wr,
                                          Issue&& issue)
 {
-    constexpr int W = kLanes3 + 2 * M;
     constexpr int NP = HI - LO;
     constexpr int NR = kRows3 + 2 * M;
     float2 Y[NR][NP];
