@@ -110,6 +110,10 @@ WAVE_EDGES = [127, 128, 129, 255, 256, 384, 511, 512, 640, 767, 768, 896, 1000, 
     (129, 12, 4, 35, [1, 17, 63, 64, 65, 100, 127, 128], False, 0, 1),
     (64, 10, 3, 35, [5, 31, 32], False, 2, 0),
     (300, 15, 3, 3, [1, 2, 150, 151, 298, 299], False, 5, 0),
+    # 11 and 15 taps: one term per chunk, an output's chunks summed over up to
+    # 5 and 7 lanes
+    (300, 15, 3, 11, [1, 2, 60, 61, 62, 150, 298, 299], False, 5, 0),
+    (257, 14, 3, 15, [1, 63, 64, 65, 127, 128, 129, 200, 256], False, 3, 0),
 ])
 def test_demigrate_kernels_at_lateral_changes(nx, nz, nw, ntaps, cuts, nan_strip, shift, dense):
     """Folded adjoint kernel (own-filter FIR plus corrections at lateral
