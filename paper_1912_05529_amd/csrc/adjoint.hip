@@ -478,9 +478,9 @@ struct FoldState {
 };
 
 // What a step hands to the next one, formed after its FIR from values it
-// loaded at its start: nothing a step starts with waits for a load (a load
-// completes in order, so a wait at the start of a step would also wait for
-// the tap refills issued at the end of the step before).
+// loaded before the FIR: nothing a step starts with waits for a load (loads
+// complete in order, so a wait at the start of a step, or at the end of the
+// step before, would also wait for the tap refills issued last).
 struct FoldCarry {
     unsigned long long mask;  // the row's change points that reach the wave's outputs (uniform)
     int mp;                   // their positions (lane i: the i-th)
