@@ -483,7 +483,7 @@ struct FoldState {
 // step before, would also wait for the tap refills issued last).
 struct FoldCarry {
     unsigned long long mask;  // the row's change points that reach the wave's outputs (uniform)
-    int mp;                   // their positions (lane i: the i-th)
+    int mp;                   // positions of all the row's change points (lane i: the i-th)
     int nb;                   // change count of the row after (uniform)
     int jp;                   // (left | right << 16) entries of its change point i_ld
     double2 img;              // image row
